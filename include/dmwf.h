@@ -1,0 +1,183 @@
+/*
+ * dmwf.h -- C ABI of the MI355X dual messenger Wiener filter library.
+ *
+ * The library solves the Wiener filter equation of Kodi Ramanah, Lavaux &
+ * Wandelt (2017), eq. (wf_equation),
+ *
+ *        (S^-1 + N^-1) s_WF = N^-1 d,
+ *
+ * for a temperature map d on the HEALPix sphere, with a diagonal signal
+ * covariance S = diag(C_l) in spherical harmonic space and a diagonal noise
+ * covariance N in pixel space (N^-1 = 0 marks masked pixels).  It uses the
+ * paper's dual messenger iteration (Section 2.2, Algorithm 2, hybrid form
+ * with cooling of xi) where the paper's flat-sky Fourier transform is replaced
+ * by the spherical harmonic transform pair on the HEALPix ring grid:
+ *
+ *   F^-1 = Y          synthesis, s(p) = sum_lm a_lm Y_lm(p)
+ *   F    = Omega Y^H  Omega = 4 pi / Npix times the adjoint of Y
+ *
+ * and the harmonic step is taken in residual form (see dmwf_dm_iterate).
+ * Everything is FP64 on one GPU.
+ *
+ * Conventions shared by every entry point
+ *   Maps    [nmaps][Npix] doubles, HEALPix RING order, Npix = 12 nside^2.
+ *   a_lm    [nmaps][n_alm][2] doubles (re, im), m-major: the slot of (l, m)
+ *           is m (2 lmax + 1 - m) / 2 + l for 0 <= m <= l <= lmax,
+ *           n_alm = (lmax+1)(lmax+2)/2.  Y_lm are orthonormal with the
+ *           Condon-Shortley phase, the field is real (a_{l,-m} =
+ *           (-1)^m conj(a_lm)); Im a_l0 is ignored on input and 0 on output.
+ *   C_l     [nmaps][lmax+1] doubles, C_l >= 0; modes with C_l = 0 stay 0.
+ *   N^-1    [nmaps][Npix] doubles, >= 0 and finite; 0 = masked.
+ *   Pointers named dev_* are device pointers owned by the caller.  The plan
+ *   owns only its constant tables.  The workspace is caller-allocated device
+ *   memory of at least dmwf_workspace_bytes() bytes, 256-byte aligned.
+ *   stream is a hipStream_t passed as void*; NULL means the null stream.
+ *   All work is enqueued on that stream.  One call at a time per plan and
+ *   workspace.
+ *   Every function validates its host-visible arguments before enqueueing
+ *   anything; on DMWF_ERR_INVALID_ARG no output is touched.  A failing HIP
+ *   call returns DMWF_ERR_HIP; dmwf_last_error() then describes it.
+ */
+#ifndef DMWF_H
+#define DMWF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DMWF_OK = 0,
+    DMWF_ERR_INVALID_ARG = 1,   /* a size, pointer or parameter is out of range    */
+    DMWF_ERR_WORKSPACE = 2,     /* workspace too small or misaligned               */
+    DMWF_ERR_HIP = 3,           /* a HIP runtime call failed                       */
+    DMWF_ERR_NOT_CONVERGED = 4, /* max_iter reached; outputs hold the last iterate */
+    DMWF_ERR_NONFINITE = 5,     /* NaN/Inf in the inputs or in the Cauchy ratio    */
+    DMWF_ERR_UNSUPPORTED = 6,   /* valid request this build does not implement     */
+    DMWF_ERR_OOM = 7            /* device allocation for the plan tables failed    */
+} dmwf_status;
+
+typedef enum { DMWF_FP64 = 0 } dmwf_precision;
+
+typedef struct dmwf_plan dmwf_plan;
+
+typedef struct {
+    int nside;     /* power of two, 1 .. 8192                                  */
+    int lmax;      /* 0 .. 3 nside - 1                                         */
+    int nmaps;     /* >= 1; maps are processed one after another             */
+    int precision; /* DMWF_FP64                                                */
+} dmwf_plan_desc;
+
+/* Cooling schedule and stopping rule of the solve (paper Algorithm 2 and
+ * Section 4).  Level k has messenger covariance xi_k: xi_0 = alpha + sigma
+ * mu0 (sigma = Npix / 4 pi), xi_{k+1} = beta xi_k, and the first value
+ * <= alpha is replaced by alpha, the last level.  A level repeats iterations
+ * until the Cauchy ratio ||s_i - s_{i-1}|| / ||s_i|| (pixel space) falls below
+ * its tolerance. */
+typedef struct {
+    double beta;             /* (0,1); <= 0 selects 0.75                          */
+    double mu0;              /* initial mu (harmonic units); < 0 selects beta*max C_l */
+    double eps_final;        /* tolerance at xi = alpha, > 0                      */
+    double eps_coarse;       /* tolerance on levels with xi > alpha, > 0          */
+    int max_iter;            /* cap on iterations per map, >= 1                   */
+    int start_final;         /* 1: run only xi = alpha, warm start from alm_out   */
+    const int* replay_iters; /* host; if non-NULL, exactly replay_iters[k]
+                                iterations on level k (n_replay = level count)    */
+    int n_replay;
+    int want_residual;       /* 1: compute stats.wf_residual (two extra transforms) */
+} dmwf_schedule;
+
+/* Per-solve statistics (host memory).  The three arrays are optional
+ * (NULL) caller buffers of cap_levels entries each. */
+typedef struct {
+    int n_levels;          /* levels run                                       */
+    int n_iter;            /* iterations run (all levels)                      */
+    double alpha;          /* min N over unmasked pixels                       */
+    double final_cauchy;   /* last Cauchy ratio                                */
+    double wf_residual;    /* ||A x - y|| / ||y||, paper Section 4 / Appendix C, or -1 */
+    int cap_levels;
+    int* iters_per_level;
+    double* xi_per_level;
+    int* lmax_per_level;   /* l_iter: largest l with C_l > mu on that level    */
+} dmwf_stats;
+
+/* Create a plan: geometry, Legendre recurrence tables and the per-(m, ring)
+ * starting values of the recurrence, built on the current device with
+ * exponent rescaling near the poles.  *out is NULL on failure. */
+dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out);
+
+/* Free the plan's tables.  NULL is accepted. */
+void dmwf_plan_destroy(dmwf_plan* plan);
+
+/* Workspace size in bytes needed by every call on this plan. */
+dmwf_status dmwf_workspace_bytes(const dmwf_plan* plan, size_t* bytes);
+
+/* Synthesis F^-1: map = Y alm for each of the plan's maps. */
+dmwf_status dmwf_alm2map(dmwf_plan* plan, const double* dev_alm, double* dev_map,
+                         void* dev_ws, size_t ws_bytes, void* stream);
+
+/* Adjoint: alm_lm = sum_p map_p conj(Y_lm(p)), times Omega = 4 pi / Npix if
+ * scale_by_pixel_area != 0 (then it is the method's forward transform F). */
+dmwf_status dmwf_adjoint(dmwf_plan* plan, const double* dev_map, double* dev_alm,
+                         int scale_by_pixel_area, void* dev_ws, size_t ws_bytes, void* stream);
+
+/* One dual messenger iteration at messenger covariance xi (paper Algorithm 2,
+ * the body of the repeat loop), single map (map 0 of the plan):
+ *
+ *   a <- f (a + Omega Y^H r),    f_l = S_bar_l / (S_bar_l + xi / sigma),
+ *                                S_bar_l = max(C_l - mu, 0), mu = (xi - alpha) / sigma
+ *   s <- Y a
+ *   cauchy2 <- (sum_p (s_p - s_prev_p)^2, sum_p s_p^2)
+ *   r <- c (d - s),              c = xi w / (1 + (xi - alpha) w),  w = N^-1
+ *
+ * r = t - s is the pixel-space messenger step with N_bar = N - alpha.  With
+ * first != 0 the residual is d on unmasked pixels (t = d, s = 0) and s_prev
+ * is taken as 0; otherwise r is the one left in the workspace by the previous
+ * call on the same plan and workspace.  dev_alm_state [n_alm][2] and
+ * dev_s_map [Npix] are read and overwritten; dev_cauchy2 receives 2 doubles.
+ * Requires alpha > 0 and xi >= alpha. */
+dmwf_status dmwf_dm_iterate(dmwf_plan* plan, double xi, double alpha, const double* dev_cl,
+                            const double* dev_d, const double* dev_ninv, double* dev_alm_state,
+                            double* dev_s_map, double* dev_cauchy2, int first,
+                            void* dev_ws, size_t ws_bytes, void* stream);
+
+/* Full solve for every map of the plan.  Outputs the Wiener filter a_lm and
+ * map s_WF = Y a_WF.  Cold start from a = 0 unless sched->start_final.  The
+ * host synchronises the stream once per iteration to read the Cauchy ratio.
+ * stats may be NULL; with nmaps > 1 it describes the last map.
+ * Returns DMWF_ERR_NONFINITE for NaN/Inf or negative values in d, N^-1 or
+ * C_l (checked on the device before the first iteration) or a NaN Cauchy
+ * ratio, DMWF_ERR_INVALID_ARG if every pixel of a map is masked, and
+ * DMWF_ERR_NOT_CONVERGED after max_iter iterations (outputs hold the last
+ * iterate). */
+dmwf_status dmwf_solve(dmwf_plan* plan, const double* dev_cl, const double* dev_d,
+                       const double* dev_ninv, const dmwf_schedule* sched,
+                       double* dev_alm_out, double* dev_map_out, dmwf_stats* stats,
+                       void* dev_ws, size_t ws_bytes, void* stream);
+
+/* ||A x - y|| / ||y|| with A = 1 + C^1/2 Y^H W Y C^1/2, x = C^-1/2 a,
+ * y = C^1/2 Y^H W d over modes with C_l > 0 (paper Section 4, Appendix C),
+ * norms on a_lm counting m > 0 twice.  Map 0; synchronises the stream. */
+dmwf_status dmwf_wf_residual(dmwf_plan* plan, const double* dev_cl, const double* dev_d,
+                             const double* dev_ninv, const double* dev_alm, double* host_out,
+                             void* dev_ws, size_t ws_bytes, void* stream);
+
+/* Kernel timing: when enabled, every launch is bracketed by HIP events on the
+ * launch stream.  dmwf_profile_read returns, for each kernel class, the launch
+ * count and the summed device time in milliseconds (it synchronises the
+ * recorded events) and clears the record.  names[i] is a static string. */
+#define DMWF_NPROF 16
+dmwf_status dmwf_profile_enable(dmwf_plan* plan, int enable);
+dmwf_status dmwf_profile_read(dmwf_plan* plan, int* n_classes, const char** names,
+                              long* counts, double* total_ms);
+
+/* Human-readable status and the last error message of the calling thread. */
+const char* dmwf_status_string(dmwf_status status);
+const char* dmwf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMWF_H */

@@ -1,0 +1,892 @@
+// C ABI of the dual messenger Wiener filter library: plans, workspace, the
+// transform entry points, one iteration, and the host-driven solve loop of
+// the paper's Algorithm 2 (cooling of xi, Cauchy stopping rule per level).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace dmwf {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+__global__ void k_set_int(int* p, int v) { *p = v; }
+
+// Largest l with C_l - mu > 0 (the Heaviside truncation of S_bar), or -1.
+__global__ void k_ell_from_cl(const double* __restrict__ cl, int lmax, double mu, int* out) {
+    int best = -1;
+    for (int l = threadIdx.x; l <= lmax; l += blockDim.x)
+        if (cl[l] - mu > 0.0) best = l;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o));
+    __shared__ int w[4];
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int b = w[0];
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) b = max(b, w[i]);
+        *out = b;
+    }
+}
+
+// a'_lm = g_lm a_lm (synthesis input), Im a_l0 dropped.  grid (l blocks, m).
+__global__ void k_prep_syn(const double2* __restrict__ alm, const double* __restrict__ g,
+                           double2* __restrict__ ap, int lmax) {
+    const int m = blockIdx.y;
+    const int l = m + blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > lmax) return;
+    const long long i = alm_base(m, lmax) + l;
+    double2 v = alm[i];
+    if (m == 0) v.y = 0.0;
+    ap[i] = make_double2(g[i] * v.x, g[i] * v.y);
+}
+
+// Harmonic step of the iteration (residual form):
+//   b = Omega g_lm sum_chunks part,  a <- f_l (a + b),  a' = g_lm a,
+//   f_l = S_bar_l / (S_bar_l + xi/sigma),  S_bar_l = max(C_l - mu, 0).
+// Slots with l > l_iter are set to zero without reading the partial sums.
+__global__ void k_diag(double2* __restrict__ a, double2* __restrict__ ap,
+                       const double2* __restrict__ part, int nchunk, size_t stride,
+                       const double* __restrict__ g, const double* __restrict__ cl, double mu,
+                       double xi_over_sigma, double omega, const int* __restrict__ ell_dev,
+                       int lmax) {
+    const int m = blockIdx.y;
+    const int l = m + blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > lmax) return;
+    const int ell = *ell_dev;
+    const long long i = alm_base(m, lmax) + l;
+    double2 out = make_double2(0.0, 0.0);
+    if (l <= ell) {
+        double sr = 0.0, si = 0.0;
+        for (int c = 0; c < nchunk; ++c) {
+            const double2 v = part[c * stride + i];
+            sr += v.x;
+            si += v.y;
+        }
+        const double sc = omega * g[i];
+        double sbar = cl[l] - mu;
+        sbar = sbar > 0.0 ? sbar : 0.0;
+        const double f = sbar / (sbar + xi_over_sigma);
+        const double2 ai = a[i];
+        out = make_double2(f * (ai.x + sc * sr), f * (ai.y + sc * si));
+        if (m == 0) out.y = 0.0;
+    }
+    a[i] = out;
+    ap[i] = make_double2(g[i] * out.x, g[i] * out.y);
+}
+
+// out_lm = scale g_lm sum_chunks part (the adjoint), all l.
+__global__ void k_adj_final(const double2* __restrict__ part, int nchunk, size_t stride,
+                            const double* __restrict__ g, double2* __restrict__ out, double scale,
+                            int lmax) {
+    const int m = blockIdx.y;
+    const int l = m + blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > lmax) return;
+    const long long i = alm_base(m, lmax) + l;
+    double sr = 0.0, si = 0.0;
+    for (int c = 0; c < nchunk; ++c) {
+        const double2 v = part[c * stride + i];
+        sr += v.x;
+        si += v.y;
+    }
+    const double sc = scale * g[i];
+    out[i] = make_double2(sc * sr, m == 0 ? 0.0 : sc * si);
+}
+
+__global__ void k_zero2(double2* p, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = make_double2(0.0, 0.0);
+}
+
+// Sum per-ring-pair pairs (num, den) into out[2] (one block, fixed order).
+__global__ void k_sum_pairs(const double* __restrict__ part, int n, double* __restrict__ out) {
+    __shared__ double sa[256], sb[256];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        a += part[2 * i];
+        b += part[2 * i + 1];
+    }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sa[threadIdx.x] += sa[threadIdx.x + s];
+            sb[threadIdx.x] += sb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sa[0];
+        out[1] = sb[0];
+    }
+}
+
+// Input screening: flags |= 1 non-finite d, 2 negative or non-finite N^-1,
+// 4 negative or non-finite C_l.  Per-block max of N^-1 into bmax[block].
+__global__ void k_check(const double* __restrict__ d, const double* __restrict__ w, long long n,
+                        const double* __restrict__ cl, int L, int* flags, double* bmax) {
+    __shared__ double sm[256];
+    int f = 0;
+    double mx = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double dv = d[i], wv = w[i];
+        if (!isfinite(dv)) f |= 1;
+        if (!isfinite(wv) || wv < 0.0) f |= 2;
+        else mx = fmax(mx, wv);
+    }
+    if (blockIdx.x == 0) {
+        for (int l = threadIdx.x; l < L; l += blockDim.x)
+            if (!isfinite(cl[l]) || cl[l] < 0.0) f |= 4;
+    }
+    if (f) atomicOr(flags, f);
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bmax[blockIdx.x] = sm[0];
+}
+
+__global__ void k_max_final(const double* __restrict__ bmax, int n, double* out) {
+    __shared__ double sm[256];
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) mx = fmax(mx, bmax[i]);
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sm[0];
+}
+
+// Residual of the whitened Wiener filter equation (paper Appendix C form):
+//   res = C^-1/2 a - C^1/2 b1,  y = C^1/2 b2   (b1 = Y^H W (d - Y a), b2 = Y^H W d)
+// over C_l > 0; per-block sums of |res|^2 and |y|^2 with m > 0 counted twice.
+__global__ void k_resid_norms(const double2* __restrict__ a, const double2* __restrict__ b1,
+                              const double2* __restrict__ b2, const double* __restrict__ cl,
+                              int lmax, double* __restrict__ bsum) {
+    __shared__ double sa[256], sb[256];
+    const int m = blockIdx.y;
+    const int l = m + blockIdx.x * blockDim.x + threadIdx.x;
+    double r2 = 0.0, y2 = 0.0;
+    if (l <= lmax && cl[l] > 0.0) {
+        const long long i = alm_base(m, lmax) + l;
+        const double c = cl[l], sq = sqrt(c), isq = 1.0 / sq;
+        const double2 av = a[i], g1 = b1[i], g2 = b2[i];
+        const double wt = m == 0 ? 1.0 : 2.0;
+        const double rx = isq * av.x - sq * g1.x;
+        const double ry = m == 0 ? 0.0 : isq * av.y - sq * g1.y;
+        const double yx = sq * g2.x, yy = m == 0 ? 0.0 : sq * g2.y;
+        r2 = wt * (rx * rx + ry * ry);
+        y2 = wt * (yx * yx + yy * yy);
+    }
+    sa[threadIdx.x] = r2;
+    sb[threadIdx.x] = y2;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sa[threadIdx.x] += sa[threadIdx.x + s];
+            sb[threadIdx.x] += sb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+        bsum[2 * b] = sa[0];
+        bsum[2 * b + 1] = sb[0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+struct Ws {
+    char* base;
+    double2* spec() const { return reinterpret_cast<double2*>(base + off.spec); }
+    double2* part() const { return reinterpret_cast<double2*>(base + off.part); }
+    double2* ap() const { return reinterpret_cast<double2*>(base + off.ap); }
+    double2* aux() const { return reinterpret_cast<double2*>(base + off.aux); }
+    double* cpart() const { return reinterpret_cast<double*>(base + off.cpart); }
+    int* ell() const { return reinterpret_cast<int*>(base + off.scal); }
+    int* flags() const { return reinterpret_cast<int*>(base + off.scal + 4); }
+    int* ell_ana() const { return reinterpret_cast<int*>(base + off.scal + 8); }
+    double* out2() const { return reinterpret_cast<double*>(base + off.scal + 16); }
+    double* scal_d() const { return reinterpret_cast<double*>(base + off.scal + 64); }
+    WsLayout off;
+};
+
+dmwf_status check_ws(const dmwf_plan* p, void* ws, size_t bytes, Ws* out) {
+    if (ws == nullptr || bytes < p->ws.total || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) {
+        set_error("workspace is missing, too small or not 256-byte aligned");
+        return DMWF_ERR_WORKSPACE;
+    }
+    out->base = static_cast<char*>(ws);
+    out->off = p->ws;
+    return DMWF_OK;
+}
+
+dim3 alm_grid(int lmax, int bs) { return dim3((lmax + 1 + bs - 1) / bs, lmax + 1); }
+
+// Number of blocks for per-pixel screening reductions (also the bmax length).
+constexpr int kCheckBlocks = 1024;
+
+size_t scal_bytes(const dmwf_plan* p) {
+    // ints + 2 doubles + block maxima + residual block sums
+    const size_t nres = 2 * (size_t)((p->lmax + 1 + 255) / 256) * (p->lmax + 1);
+    return 64 + sizeof(double) * (kCheckBlocks + 8 + nres);
+}
+
+}  // namespace
+}  // namespace dmwf
+
+using namespace dmwf;
+
+extern "C" {
+
+const char* dmwf_status_string(dmwf_status s) {
+    switch (s) {
+        case DMWF_OK: return "ok";
+        case DMWF_ERR_INVALID_ARG: return "invalid argument";
+        case DMWF_ERR_WORKSPACE: return "workspace too small or misaligned";
+        case DMWF_ERR_HIP: return "HIP runtime error";
+        case DMWF_ERR_NOT_CONVERGED: return "not converged within max_iter";
+        case DMWF_ERR_NONFINITE: return "non-finite or negative input, or non-finite Cauchy ratio";
+        case DMWF_ERR_UNSUPPORTED: return "unsupported";
+        case DMWF_ERR_OOM: return "device allocation failed";
+    }
+    return "unknown status";
+}
+
+const char* dmwf_last_error(void) { return g_last_error.c_str(); }
+
+void dmwf_plan_destroy(dmwf_plan* p) {
+    if (!p) return;
+    for (auto& e : p->events) {
+        (void)hipEventDestroy(e.start);
+        (void)hipEventDestroy(e.stop);
+    }
+    void* bufs[] = {p->d_x, p->d_sint, p->d_nph, p->d_phi0pi, p->d_start_n, p->d_start_s,
+                    p->d_A, p->d_g,    p->d_ls,  p->d_s0,     p->d_s1};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    delete p;
+}
+
+dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
+    if (!out) {
+        set_error("out is NULL");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (!desc) {
+        set_error("desc is NULL");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    const int N = desc->nside;
+    if (N < 1 || N > 8192 || (N & (N - 1)) != 0) {
+        set_error("nside must be a power of two in [1, 8192]");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    if (desc->lmax < 0 || desc->lmax > 3 * N - 1) {
+        set_error("lmax must be in [0, 3 nside - 1]");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    if (desc->nmaps < 1) {
+        set_error("nmaps must be >= 1");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    if (desc->precision != DMWF_FP64) {
+        set_error("only DMWF_FP64 is implemented");
+        return DMWF_ERR_UNSUPPORTED;
+    }
+    dmwf_plan* p = new dmwf_plan();
+    p->nside = N;
+    p->lmax = desc->lmax;
+    p->nmaps = desc->nmaps;
+    p->nq = 2 * N;
+    p->nrings = 4 * N - 1;
+    p->npix = 12LL * N * N;
+    p->nalm = (long long)(p->lmax + 1) * (p->lmax + 2) / 2;
+    p->omega = 4.0 * kPi / (double)p->npix;
+    p->nchunk_syn = (p->nq + 64 * kSynK - 1) / (64 * kSynK);
+    p->nchunk_ana = (p->nq + 64 * kAnaK - 1) / (64 * kAnaK);
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        set_error("hipGetDevice failed");
+        delete p;
+        return DMWF_ERR_HIP;
+    }
+
+    // ---- ring pair geometry (HEALPix RING scheme) ----
+    const int nq = p->nq;
+    std::vector<double> x(nq), st(nq), phi0pi(nq);
+    std::vector<int> nph(nq);
+    std::vector<long long> sn(nq), ss(nq);
+    const long double LN = N;
+    for (int q = 0; q < nq; ++q) {
+        const long long r = q + 1;  // north ring, 1-based; r = 2N is the equator
+        long double z, s;
+        if (r < N) {
+            const long double u = (long double)r * r / (3.0L * LN * LN);  // 1 - z
+            z = 1.0L - u;
+            s = sqrtl(u * (2.0L - u));
+            nph[q] = (int)(4 * r);
+            phi0pi[q] = (double)(1.0L / (4.0L * r));
+            sn[q] = 2 * r * (r - 1);
+            ss[q] = p->npix - 2 * r * (r + 1);
+        } else {
+            z = 4.0L / 3.0L - 2.0L * r / (3.0L * LN);
+            s = sqrtl((1.0L - z) * (1.0L + z));
+            nph[q] = 4 * N;
+            const int shift = (int)((r - N + 1) % 2);
+            phi0pi[q] = shift ? (double)(1.0L / (4.0L * LN)) : 0.0;
+            sn[q] = 2LL * N * (N - 1) + 4LL * N * (r - N);
+            const long long rs = 4LL * N - r;
+            ss[q] = (r == 2LL * N) ? -1 : 2LL * N * (N - 1) + 4LL * N * (rs - N);
+        }
+        x[q] = (double)z;
+        st[q] = (double)s;
+    }
+
+    // ---- recurrence tables: lambda_lm = g_lm mu_lm, mu_l = A_l x mu_{l-1} - mu_{l-2} ----
+    const int L = p->lmax;
+    const size_t ntab = (size_t)p->nalm + kTablePad;
+    std::vector<double> A(ntab, 0.0), G(ntab, 0.0);
+    for (int m = 0; m <= L; ++m) {
+        const long long b = alm_base(m, L);
+        long double gm2 = 1.0L, gm1 = 1.0L, am1 = 0.0L;  // g_{l-2}, g_{l-1}, a_{l-1}
+        G[b + m] = 1.0;
+        A[b + m] = 0.0;
+        for (int l = m + 1; l <= L; ++l) {
+            const long double dl = l, dm = m;
+            const long double al = sqrtl((4.0L * dl * dl - 1.0L) / (dl * dl - dm * dm));
+            long double gl;
+            if (l == m + 1) {
+                gl = 1.0L;
+            } else {
+                gl = gm2 * al / am1;
+            }
+            A[b + l] = (double)(al * gm1 / gl);
+            G[b + l] = (double)gl;
+            gm2 = gm1;
+            gm1 = gl;
+            am1 = al;
+        }
+    }
+
+    auto fail = [&](dmwf_status st_) {
+        dmwf_plan_destroy(p);
+        return st_;
+    };
+    auto up = [&](void** dst, const void* src, size_t bytes) -> bool {
+        if (hipMalloc(dst, bytes) != hipSuccess) return false;
+        return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (!up((void**)&p->d_x, x.data(), nq * sizeof(double)) ||
+        !up((void**)&p->d_sint, st.data(), nq * sizeof(double)) ||
+        !up((void**)&p->d_nph, nph.data(), nq * sizeof(int)) ||
+        !up((void**)&p->d_phi0pi, phi0pi.data(), nq * sizeof(double)) ||
+        !up((void**)&p->d_start_n, sn.data(), nq * sizeof(long long)) ||
+        !up((void**)&p->d_start_s, ss.data(), nq * sizeof(long long)) ||
+        !up((void**)&p->d_A, A.data(), ntab * sizeof(double)) ||
+        !up((void**)&p->d_g, G.data(), ntab * sizeof(double))) {
+        set_error("allocation or upload of plan tables failed");
+        return fail(DMWF_ERR_OOM);
+    }
+    const size_t nseed = (size_t)(L + 1) * nq;
+    if (hipMalloc(&p->d_ls, nseed * sizeof(int)) != hipSuccess ||
+        hipMalloc(&p->d_s0, nseed * sizeof(double)) != hipSuccess ||
+        hipMalloc(&p->d_s1, nseed * sizeof(double)) != hipSuccess) {
+        set_error("allocation of recurrence start tables failed");
+        return fail(DMWF_ERR_OOM);
+    }
+    dmwf_status s = launch_seeds(p, nullptr);
+    if (s != DMWF_OK) return fail(s);
+
+    // ---- workspace layout ----
+    WsLayout& w = p->ws;
+    size_t off = 0;
+    w.spec = off;
+    off = align256(off + (size_t)(L + 1) * nq * 2 * sizeof(double2));
+    w.part = off;
+    off = align256(off + (size_t)p->nchunk_ana * ntab * sizeof(double2));
+    w.ap = off;
+    off = align256(off + ntab * sizeof(double2));
+    w.aux = off;
+    off = align256(off + ntab * sizeof(double2));
+    w.cpart = off;
+    off = align256(off + (size_t)nq * 2 * sizeof(double));
+    w.scal = off;
+    off = align256(off + scal_bytes(p));
+    w.total = off;
+    *out = p;
+    return DMWF_OK;
+}
+
+dmwf_status dmwf_workspace_bytes(const dmwf_plan* p, size_t* bytes) {
+    if (!p || !bytes) {
+        set_error("NULL argument");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    *bytes = p->ws.total;
+    return DMWF_OK;
+}
+
+dmwf_status dmwf_profile_enable(dmwf_plan* p, int enable) {
+    if (!p) return DMWF_ERR_INVALID_ARG;
+    p->prof = enable != 0;
+    return DMWF_OK;
+}
+
+dmwf_status dmwf_profile_read(dmwf_plan* p, int* n_classes, const char** names, long* counts,
+                              double* total_ms) {
+    static const char* kNames[PROF_COUNT] = {"seeds", "legendre_analysis", "legendre_synthesis",
+                                             "harmonic_diag", "ring_iter", "ring_synthesis",
+                                             "ring_analysis", "reduce", "misc"};
+    if (!p || !n_classes) return DMWF_ERR_INVALID_ARG;
+    *n_classes = PROF_COUNT;
+    for (int i = 0; i < PROF_COUNT; ++i) {
+        if (names) names[i] = kNames[i];
+        if (counts) counts[i] = 0;
+        if (total_ms) total_ms[i] = 0.0;
+    }
+    for (auto& e : p->events) {
+        DMWF_HIP(hipEventSynchronize(e.stop));
+        float ms = 0.0f;
+        DMWF_HIP(hipEventElapsedTime(&ms, e.start, e.stop));
+        if (counts) counts[e.cls] += 1;
+        if (total_ms) total_ms[e.cls] += ms;
+        (void)hipEventDestroy(e.start);
+        (void)hipEventDestroy(e.stop);
+    }
+    p->events.clear();
+    return DMWF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// transforms
+// ---------------------------------------------------------------------------
+dmwf_status dmwf_alm2map(dmwf_plan* p, const double* alm, double* map, void* ws, size_t ws_bytes,
+                         void* stream) {
+    if (!p || !alm || !map) {
+        set_error("NULL argument");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    Ws W;
+    dmwf_status st = check_ws(p, ws, ws_bytes, &W);
+    if (st != DMWF_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int k = 0; k < p->nmaps; ++k) {
+        const double2* a = reinterpret_cast<const double2*>(alm) + (size_t)k * p->nalm;
+        double* mp = map + (size_t)k * p->npix;
+        {
+            ProfScope ps(p, s, PROF_MISC);
+            hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell(), p->lmax);
+            hipLaunchKernelGGL(k_prep_syn, alm_grid(p->lmax, 256), dim3(256), 0, s, a, p->d_g,
+                               W.ap(), p->lmax);
+        }
+        DMWF_HIP(hipGetLastError());
+        st = launch_leg_syn(p, W.ap(), W.spec(), W.ell(), s);
+        if (st != DMWF_OK) return st;
+        RingIO io{};
+        io.map_out = mp;
+        st = launch_ring(p, RING_SYN, W.spec(), W.ell(), W.ell(), io, s);
+        if (st != DMWF_OK) return st;
+    }
+    return DMWF_OK;
+}
+
+dmwf_status dmwf_adjoint(dmwf_plan* p, const double* map, double* alm, int scale_by_pixel_area,
+                         void* ws, size_t ws_bytes, void* stream) {
+    if (!p || !alm || !map) {
+        set_error("NULL argument");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    Ws W;
+    dmwf_status st = check_ws(p, ws, ws_bytes, &W);
+    if (st != DMWF_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int k = 0; k < p->nmaps; ++k) {
+        double2* a = reinterpret_cast<double2*>(alm) + (size_t)k * p->nalm;
+        const double* mp = map + (size_t)k * p->npix;
+        {
+            ProfScope ps(p, s, PROF_MISC);
+            hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell(), p->lmax);
+        }
+        RingIO io{};
+        io.map_in = mp;
+        st = launch_ring(p, RING_ANA, W.spec(), W.ell(), W.ell(), io, s);
+        if (st != DMWF_OK) return st;
+        st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), s);
+        if (st != DMWF_OK) return st;
+        {
+            ProfScope ps(p, s, PROF_DIAG);
+            hipLaunchKernelGGL(k_adj_final, alm_grid(p->lmax, 256), dim3(256), 0, s, W.part(),
+                               p->nchunk_ana, (size_t)p->nalm + kTablePad, p->d_g, a,
+                               scale_by_pixel_area ? p->omega : 1.0, p->lmax);
+        }
+        DMWF_HIP(hipGetLastError());
+    }
+    return DMWF_OK;
+}
+
+}  // extern "C"
+
+namespace dmwf {
+namespace {
+
+// The iteration body shared by dmwf_dm_iterate and the solve loop: harmonic
+// step from the residual spectrum in the workspace, synthesis, pixel step.
+dmwf_status iterate_body(dmwf_plan* p, const Ws& W, double xi, double alpha, double mu,
+                         const double* cl, const double* d, const double* w, double2* a,
+                         double* s_map, int first_pix, hipStream_t s) {
+    dmwf_status st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), s);
+    if (st != DMWF_OK) return st;
+    {
+        ProfScope ps(p, s, PROF_DIAG);
+        hipLaunchKernelGGL(k_diag, alm_grid(p->lmax, 256), dim3(256), 0, s, a, W.ap(), W.part(),
+                           p->nchunk_ana, (size_t)p->nalm + kTablePad, p->d_g, cl, mu,
+                           xi * p->omega, p->omega, W.ell(), p->lmax);
+    }
+    DMWF_HIP(hipGetLastError());
+    st = launch_leg_syn(p, W.ap(), W.spec(), W.ell(), s);
+    if (st != DMWF_OK) return st;
+    RingIO io{};
+    io.d = d;
+    io.w = w;
+    io.s_map = s_map;
+    io.cpart = W.cpart();
+    io.xi = xi;
+    io.alpha = alpha;
+    io.first = first_pix;
+    st = launch_ring(p, RING_ITER, W.spec(), W.ell(), W.ell_ana(), io, s);
+    if (st != DMWF_OK) return st;
+    {
+        ProfScope ps(p, s, PROF_REDUCE);
+        hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, s, W.cpart(), p->nq, W.out2());
+    }
+    DMWF_HIP(hipGetLastError());
+    return DMWF_OK;
+}
+
+dmwf_status residual_map(dmwf_plan* p, const Ws& W, const double* cl, const double* d,
+                         const double* w, const double2* a, double* host_out, hipStream_t s) {
+    // b1 = Y^H W (d - Y a) into ap (after its use as synthesis input), b2 = Y^H W d into aux
+    {
+        ProfScope ps(p, s, PROF_MISC);
+        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell(), p->lmax);
+        hipLaunchKernelGGL(k_prep_syn, alm_grid(p->lmax, 256), dim3(256), 0, s, a, p->d_g, W.ap(),
+                           p->lmax);
+    }
+    DMWF_HIP(hipGetLastError());
+    dmwf_status st = launch_leg_syn(p, W.ap(), W.spec(), W.ell(), s);
+    if (st != DMWF_OK) return st;
+    RingIO io{};
+    io.d = d;
+    io.w = w;
+    st = launch_ring(p, RING_SYN_WRES, W.spec(), W.ell(), W.ell(), io, s);
+    if (st != DMWF_OK) return st;
+    st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), s);
+    if (st != DMWF_OK) return st;
+    const size_t stride = (size_t)p->nalm + kTablePad;
+    hipLaunchKernelGGL(k_adj_final, alm_grid(p->lmax, 256), dim3(256), 0, s, W.part(),
+                       p->nchunk_ana, stride, p->d_g, W.ap(), 1.0, p->lmax);
+    st = launch_ring(p, RING_ANA_WD, W.spec(), W.ell(), W.ell(), io, s);
+    if (st != DMWF_OK) return st;
+    st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), s);
+    if (st != DMWF_OK) return st;
+    hipLaunchKernelGGL(k_adj_final, alm_grid(p->lmax, 256), dim3(256), 0, s, W.part(),
+                       p->nchunk_ana, stride, p->d_g, W.aux(), 1.0, p->lmax);
+    const dim3 gr = alm_grid(p->lmax, 256);
+    double* bsum = W.scal_d() + kCheckBlocks + 8;
+    hipLaunchKernelGGL(k_resid_norms, gr, dim3(256), 0, s, a, W.ap(), W.aux(), cl, p->lmax, bsum);
+    const int nb = (int)(gr.x * gr.y);
+    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, s, bsum, nb, W.out2());
+    DMWF_HIP(hipGetLastError());
+    double h[2];
+    DMWF_HIP(hipMemcpyAsync(h, W.out2(), sizeof(h), hipMemcpyDeviceToHost, s));
+    DMWF_HIP(hipStreamSynchronize(s));
+    *host_out = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : (h[0] == 0.0 ? 0.0 : INFINITY);
+    return DMWF_OK;
+}
+
+}  // namespace
+}  // namespace dmwf
+
+extern "C" {
+
+dmwf_status dmwf_dm_iterate(dmwf_plan* p, double xi, double alpha, const double* cl,
+                            const double* d, const double* ninv, double* alm_state, double* s_map,
+                            double* cauchy2, int first, void* ws, size_t ws_bytes, void* stream) {
+    if (!p || !cl || !d || !ninv || !alm_state || !s_map || !cauchy2) {
+        set_error("NULL argument");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    if (!(alpha > 0.0) || !(xi >= alpha) || !std::isfinite(xi)) {
+        set_error("need 0 < alpha <= xi < inf");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    Ws W;
+    dmwf_status st = check_ws(p, ws, ws_bytes, &W);
+    if (st != DMWF_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double mu = (xi - alpha) / (1.0 / p->omega);
+    {
+        ProfScope ps(p, s, PROF_MISC);
+        hipLaunchKernelGGL(k_ell_from_cl, dim3(1), dim3(256), 0, s, cl, p->lmax, mu, W.ell());
+        // the residual spectrum left for the next call covers every m, so a
+        // later call at a smaller xi (larger l_iter) finds it complete
+        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell_ana(), p->lmax);
+    }
+    DMWF_HIP(hipGetLastError());
+    if (first) {
+        RingIO io{};
+        io.d = d;
+        io.w = ninv;
+        st = launch_ring(p, RING_ANA_FIRST, W.spec(), W.ell_ana(), W.ell_ana(), io, s);
+        if (st != DMWF_OK) return st;
+    }
+    st = iterate_body(p, W, xi, alpha, mu, cl, d, ninv, reinterpret_cast<double2*>(alm_state),
+                      s_map, first ? 1 : 0, s);
+    if (st != DMWF_OK) return st;
+    DMWF_HIP(hipMemcpyAsync(cauchy2, W.out2(), 2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return DMWF_OK;
+}
+
+dmwf_status dmwf_wf_residual(dmwf_plan* p, const double* cl, const double* d, const double* ninv,
+                             const double* alm, double* host_out, void* ws, size_t ws_bytes,
+                             void* stream) {
+    if (!p || !cl || !d || !ninv || !alm || !host_out) {
+        set_error("NULL argument");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    Ws W;
+    dmwf_status st = check_ws(p, ws, ws_bytes, &W);
+    if (st != DMWF_OK) return st;
+    return residual_map(p, W, cl, d, ninv, reinterpret_cast<const double2*>(alm), host_out,
+                        static_cast<hipStream_t>(stream));
+}
+
+dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
+                       const double* ninv_all, const dmwf_schedule* sc, double* alm_all,
+                       double* map_all, dmwf_stats* stats, void* ws, size_t ws_bytes,
+                       void* stream) {
+    if (!p || !cl_all || !d_all || !ninv_all || !sc || !alm_all || !map_all) {
+        set_error("NULL argument");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    const double beta = sc->beta > 0.0 ? sc->beta : 0.75;
+    if (!(beta < 1.0) || !(sc->eps_final > 0.0) || !(sc->eps_coarse > 0.0) || sc->max_iter < 1 ||
+        (sc->replay_iters && sc->n_replay < 1)) {
+        set_error("schedule: need 0 < beta < 1, eps > 0, max_iter >= 1");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    if (stats && stats->cap_levels < 0) {
+        set_error("stats.cap_levels < 0");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    Ws W;
+    dmwf_status st = check_ws(p, ws, ws_bytes, &W);
+    if (st != DMWF_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int L = p->lmax;
+    const double sigma = 1.0 / p->omega;
+    dmwf_status result = DMWF_OK;
+
+    for (int k = 0; k < p->nmaps; ++k) {
+        const double* cl = cl_all + (size_t)k * (L + 1);
+        const double* d = d_all + (size_t)k * p->npix;
+        const double* w = ninv_all + (size_t)k * p->npix;
+        double2* a = reinterpret_cast<double2*>(alm_all) + (size_t)k * p->nalm;
+        double* smap = map_all + (size_t)k * p->npix;
+
+        // a0: screen the inputs and find alpha = 1 / max N^-1
+        double* bmax = W.scal_d();
+        {
+            ProfScope ps(p, s, PROF_MISC);
+            hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.flags(), 0);
+            hipLaunchKernelGGL(k_check, dim3(kCheckBlocks), dim3(256), 0, s, d, w, p->npix, cl,
+                               L + 1, W.flags(), bmax);
+            hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, bmax, kCheckBlocks,
+                               W.out2());
+        }
+        DMWF_HIP(hipGetLastError());
+        int flags = 0;
+        double wmax = 0.0;
+        std::vector<double> hcl(L + 1);
+        DMWF_HIP(hipMemcpyAsync(&flags, W.flags(), sizeof(int), hipMemcpyDeviceToHost, s));
+        DMWF_HIP(hipMemcpyAsync(&wmax, W.out2(), sizeof(double), hipMemcpyDeviceToHost, s));
+        DMWF_HIP(hipMemcpyAsync(hcl.data(), cl, (L + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        DMWF_HIP(hipStreamSynchronize(s));
+        if (flags) {
+            set_error("non-finite or negative values in d, N^-1 or C_l");
+            return DMWF_ERR_NONFINITE;
+        }
+        if (!(wmax > 0.0)) {
+            set_error("every pixel is masked (N^-1 = 0 everywhere)");
+            return DMWF_ERR_INVALID_ARG;
+        }
+        const double alpha = 1.0 / wmax;
+
+        // a1: the level schedule
+        double clmax = 0.0;
+        for (double v : hcl) clmax = std::max(clmax, v);
+        std::vector<double> xis;
+        if (sc->start_final) {
+            xis.push_back(alpha);
+        } else {
+            const double mu0 = sc->mu0 < 0.0 ? beta * clmax : sc->mu0;
+            double xi = alpha + sigma * mu0;
+            while (xi > alpha) {
+                xis.push_back(xi);
+                xi = beta * xi;
+            }
+            xis.push_back(alpha);
+        }
+        if (sc->replay_iters && sc->n_replay != (int)xis.size()) {
+            set_error("replay_iters has " + std::to_string(sc->n_replay) + " levels, schedule has " +
+                      std::to_string(xis.size()));
+            return DMWF_ERR_INVALID_ARG;
+        }
+
+        // start
+        int first_pix = 0;
+        if (sc->start_final) {
+            // s = Y a0, r = c (d - s) at xi = alpha
+            {
+                ProfScope ps(p, s, PROF_MISC);
+                hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell(), L);
+                hipLaunchKernelGGL(k_prep_syn, alm_grid(L, 256), dim3(256), 0, s, a, p->d_g,
+                                   W.ap(), L);
+            }
+            st = launch_leg_syn(p, W.ap(), W.spec(), W.ell(), s);
+            if (st != DMWF_OK) return st;
+            RingIO io{};
+            io.map_out = smap;
+            st = launch_ring(p, RING_SYN, W.spec(), W.ell(), W.ell(), io, s);
+            if (st != DMWF_OK) return st;
+            io = RingIO{};
+            io.map_in = smap;
+            io.d = d;
+            io.w = w;
+            io.xi = alpha;
+            io.alpha = alpha;
+            st = launch_ring(p, RING_ANA_CRES, W.spec(), W.ell(), W.ell(), io, s);
+            if (st != DMWF_OK) return st;
+        } else {
+            {
+                ProfScope ps(p, s, PROF_MISC);
+                hipLaunchKernelGGL(k_zero2, dim3(256), dim3(256), 0, s, a, p->nalm);
+                hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell(), L);
+            }
+            RingIO io{};
+            io.d = d;
+            io.w = w;
+            st = launch_ring(p, RING_ANA_FIRST, W.spec(), W.ell(), W.ell(), io, s);
+            if (st != DMWF_OK) return st;
+            first_pix = 1;
+        }
+        DMWF_HIP(hipGetLastError());
+
+        int total = 0, nlev = 0, ell_prev = L;
+        double ratio = 0.0;
+        bool capped = false;
+        double h2[2];
+        for (size_t lev = 0; lev < xis.size() && !capped; ++lev) {
+            const double xi = xis[lev];
+            const double mu = (xi - alpha) / sigma;
+            int ell = -1;
+            for (int l = 0; l <= L; ++l)
+                if (hcl[l] - mu > 0.0) ell = l;
+            if (lev > 0 && ell > ell_prev) {
+                // The residual r = c(xi_prev) (d - s) carried into this level was
+                // analysed only for m <= l_iter of the previous level; redo it
+                // for every m this level uses.
+                {
+                    ProfScope ps(p, s, PROF_MISC);
+                    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell(), ell);
+                }
+                RingIO io{};
+                io.map_in = smap;
+                io.d = d;
+                io.w = w;
+                io.xi = xis[lev - 1];
+                io.alpha = alpha;
+                st = launch_ring(p, RING_ANA_CRES, W.spec(), W.ell(), W.ell(), io, s);
+                if (st != DMWF_OK) return st;
+            }
+            {
+                ProfScope ps(p, s, PROF_MISC);
+                hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell(), ell);
+                hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell_ana(), ell);
+            }
+            ell_prev = ell;
+            const double eps = xi <= alpha ? sc->eps_final : sc->eps_coarse;
+            int it = 0;
+            while (true) {
+                st = iterate_body(p, W, xi, alpha, mu, cl, d, w, a, smap, first_pix, s);
+                if (st != DMWF_OK) return st;
+                first_pix = 0;
+                DMWF_HIP(hipMemcpyAsync(h2, W.out2(), sizeof(h2), hipMemcpyDeviceToHost, s));
+                DMWF_HIP(hipStreamSynchronize(s));
+                ++it;
+                ++total;
+                ratio = h2[1] > 0.0 ? std::sqrt(h2[0] / h2[1]) : (h2[0] == 0.0 ? 0.0 : INFINITY);
+                if (std::isnan(ratio)) {
+                    set_error("Cauchy ratio is NaN");
+                    return DMWF_ERR_NONFINITE;
+                }
+                if (sc->replay_iters) {
+                    if (it >= sc->replay_iters[lev]) break;
+                } else if (ratio < eps) {
+                    break;
+                }
+                if (total >= sc->max_iter) {
+                    capped = true;
+                    break;
+                }
+            }
+            if (stats && (int)lev < stats->cap_levels) {
+                if (stats->iters_per_level) stats->iters_per_level[lev] = it;
+                if (stats->xi_per_level) stats->xi_per_level[lev] = xi;
+                if (stats->lmax_per_level) stats->lmax_per_level[lev] = ell;
+            }
+            ++nlev;
+        }
+        if (stats) {
+            stats->n_levels = nlev;
+            stats->n_iter = total;
+            stats->alpha = alpha;
+            stats->final_cauchy = ratio;
+            stats->wf_residual = -1.0;
+        }
+        if (sc->want_residual && stats) {
+            double res = 0.0;
+            st = residual_map(p, W, cl, d, w, a, &res, s);
+            if (st != DMWF_OK) return st;
+            stats->wf_residual = res;
+        }
+        if (capped) result = DMWF_ERR_NOT_CONVERGED;
+    }
+    return result;
+}
+
+}  // extern "C"

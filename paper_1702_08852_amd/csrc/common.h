@@ -1,0 +1,176 @@
+// Internal declarations shared by the HIP sources of the dual messenger library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dmwf.h"
+
+namespace dmwf {
+
+// Rings per lane in the Legendre kernels: a wave covers 64*K ring pairs.
+constexpr int kSynK = 4;
+constexpr int kAnaK = 4;
+// l values per analysis reduction block.
+constexpr int kAnaB = 16;
+// Padding (entries) after the per-(l,m) tables so that look-ahead reads of
+// the recurrence coefficients stay inside the allocation.
+constexpr int kTablePad = 64;
+// A term lambda_lm with |lambda_lm| below 2^kSkipLog2 is treated as zero:
+// the recurrence starts at the first l where the magnitude reaches it.
+constexpr int kSkipLog2 = -100;
+// Sentinel start index for (m, ring) pairs that never reach the threshold.
+constexpr int kNever = 0x3fffffff;
+
+enum ProfClass {
+    PROF_SEED = 0,
+    PROF_LEG_ANA,
+    PROF_LEG_SYN,
+    PROF_DIAG,
+    PROF_RING_ITER,
+    PROF_RING_SYN,
+    PROF_RING_ANA,
+    PROF_REDUCE,
+    PROF_MISC,
+    PROF_COUNT
+};
+
+struct ProfEvent {
+    int cls;
+    hipEvent_t start, stop;
+};
+
+// Device-side description of the ring grid, one entry per ring pair q:
+// q < 2N-1 pairs north ring q+1 with south ring 4N-1-q (1-based ring numbers),
+// q = 2N-1 is the equator alone.
+struct RingGeom {
+    const double* x;          // cos(theta) of the north ring
+    const double* sint;       // sin(theta)
+    const int* nph;           // pixels in each ring of the pair
+    const double* phi0pi;     // phi of the first pixel divided by pi
+    const long long* start_n; // first pixel of the north ring
+    const long long* start_s; // first pixel of the south ring, -1 for the equator
+};
+
+// Workspace layout (byte offsets from the workspace base).
+struct WsLayout {
+    size_t spec;    // complex [(lmax+1)][nq][2]: ring Fourier coefficients F_m / G_m
+    size_t part;    // complex [nchunk_ana][n_alm + pad]: analysis partial sums
+    size_t ap;      // complex [n_alm + pad]: g-scaled a_lm for the synthesis
+    size_t aux;     // complex [n_alm + pad]: second a_lm-sized buffer
+    size_t cpart;   // double  [nq][2]: Cauchy partial sums per ring pair
+    size_t scal;    // small scalars: ints and doubles
+    size_t total;
+};
+
+}  // namespace dmwf
+
+struct dmwf_plan {
+    int nside, lmax, nmaps, nq, nrings, device;
+    long long npix, nalm;
+    int nchunk_ana, nchunk_syn;
+    double omega;  // 4 pi / Npix
+    // device tables
+    double* d_x = nullptr;
+    double* d_sint = nullptr;
+    int* d_nph = nullptr;
+    double* d_phi0pi = nullptr;
+    long long* d_start_n = nullptr;
+    long long* d_start_s = nullptr;
+    double* d_A = nullptr;  // recurrence multipliers A_lm, m-major, + pad
+    double* d_g = nullptr;  // scale g_lm with lambda_lm = g_lm mu_lm, + pad
+    int* d_ls = nullptr;    // [(lmax+1)][nq] first significant l
+    double* d_s0 = nullptr; // mu at ls-1
+    double* d_s1 = nullptr; // mu at ls
+    dmwf::WsLayout ws;
+    // profiling
+    bool prof = false;
+    std::vector<dmwf::ProfEvent> events;
+    dmwf::RingGeom geom() const {
+        return {d_x, d_sint, d_nph, d_phi0pi, d_start_n, d_start_s};
+    }
+};
+
+namespace dmwf {
+
+void set_error(const std::string& msg);
+
+// Check a HIP call; on failure record the message and return DMWF_ERR_HIP.
+#define DMWF_HIP(call)                                                          \
+    do {                                                                        \
+        hipError_t e_ = (call);                                                 \
+        if (e_ != hipSuccess) {                                                 \
+            ::dmwf::set_error(std::string(#call) + ": " + hipGetErrorString(e_)); \
+            return DMWF_ERR_HIP;                                                \
+        }                                                                       \
+    } while (0)
+
+// Bracket a launch with profiling events when enabled.
+struct ProfScope {
+    dmwf_plan* p;
+    hipStream_t s;
+    int cls;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(dmwf_plan* p_, hipStream_t s_, int c_) : p(p_), s(s_), cls(c_) {
+        if (p->prof) {
+            (void)hipEventCreate(&a);
+            (void)hipEventCreate(&b);
+            (void)hipEventRecord(a, s);
+        }
+    }
+    ~ProfScope() {
+        if (p->prof) {
+            (void)hipEventRecord(b, s);
+            p->events.push_back({cls, a, b});
+        }
+    }
+};
+
+__host__ __device__ inline long long alm_base(int m, int lmax) {
+    // slot of (l, m) is alm_base(m) + l
+    return (long long)m * (2LL * lmax + 1 - m) / 2;
+}
+
+// ---- launchers (ring.hip, legendre.hip, api.hip) ----
+dmwf_status launch_seeds(dmwf_plan* p, hipStream_t s);
+dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const int* ell_dev,
+                           hipStream_t s);
+dmwf_status launch_leg_ana(dmwf_plan* p, const double2* spec, double2* part, const int* ell_dev,
+                           hipStream_t s);
+
+// Ring stage modes.  SYN: F -> map.  ANA*: a pixel map -> G, the map being
+// map_in (ANA), d on unmasked pixels (ANA_FIRST), w (d - map_in) (ANA_RESID),
+// w d (ANA_WD) or c (d - map_in) with the pixel-step coefficient c (ANA_CRES).
+// ITER: F -> s (Cauchy sums, s_map updated) -> r = c (d - s) -> G.
+// SYN_WRES: F -> s (not stored) -> r = w (d - s) -> G.
+enum RingMode {
+    RING_SYN = 0,
+    RING_ANA,
+    RING_ANA_FIRST,
+    RING_ANA_RESID,
+    RING_ANA_WD,
+    RING_ANA_CRES,
+    RING_ITER,
+    RING_SYN_WRES
+};
+struct RingIO {
+    double* map_out;        // RING_SYN: synthesised map
+    const double* map_in;   // RING_ANA: map to analyse
+    const double* d;        // data
+    const double* w;        // N^-1
+    double* s_map;          // RING_ITER: s_prev in, s out
+    double* cpart;          // RING_ITER: Cauchy partials [nq][2]
+    double xi, alpha;       // RING_ITER: pixel step coefficients
+    int first;              // RING_ITER: s_prev taken as 0
+};
+// ell_syn bounds the m of F used by the synthesis, ell_ana the m of G written
+// by the analysis (device scalars).
+dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const int* ell_syn,
+                        const int* ell_ana, const RingIO& io, hipStream_t s);
+size_t ring_lds_bytes(const dmwf_plan* p);
+
+}  // namespace dmwf

@@ -1,0 +1,385 @@
+// Legendre stage of the spherical harmonic transform pair on the HEALPix
+// ring grid (the m-by-m part of the paper's basis change F / F^-1, Algorithm 2,
+// moved to the sphere).
+//
+// For every m and every ring pair q (north ring at x = cos(theta), south ring
+// at -x):
+//   synthesis  F_m(north) = E + O,  F_m(south) = E - O,
+//              E = sum_{l-m even} lambda_lm(x) a_lm,  O = sum_{l-m odd} lambda_lm(x) a_lm
+//   analysis   b_lm = sum_q lambda_lm(x_q) [G_m(north_q) + (-1)^{l-m} G_m(south_q)]
+//
+// lambda_lm = g_lm mu_lm where mu obeys the two-term-cost recurrence
+//   mu_l = (A_l x) mu_{l-1} - mu_{l-2},
+// so one recurrence step is a multiply and an FMA.  The synthesis input is
+// pre-scaled (a'_lm = g_lm a_lm) and the analysis output is post-scaled by
+// g_lm, both outside these kernels.
+//
+// Near the poles lambda_lm underflows for l well below the turning point.  The
+// plan stores, per (m, q), the first l with |lambda_lm| >= 2^-100 and the
+// values mu_{l-1}, mu_l there, computed with exponent rescaling; the kernels
+// start each ring at that l and treat the terms before it as zero.
+//
+// Mapping: one wave per (m, chunk of 64*K ring pairs); lane = ring pair, each
+// lane carries K ring pairs spaced 64 apart.  The recurrence runs in l inside
+// a lane, so the synthesis sum over l needs no communication; the analysis sum
+// over rings is reduced across lanes through LDS once per block of 16 l.
+#include <climits>
+
+#include "common.h"
+
+namespace dmwf {
+namespace {
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// lambda_mm(x_q) for m = 0..lmax as mant * 2^expo: lambda_00 = 1/sqrt(4 pi),
+// lambda_mm = -sqrt((2m+1)/(2m)) sin(theta) lambda_{m-1,m-1}.  The mantissa is
+// renormalised by 2^256 whenever it drops below 2^-256.
+__global__ void k_seed_mm(int lmax, int nq, const double* __restrict__ sint,
+                          double* __restrict__ mant, int* __restrict__ expo) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const double st = sint[q];
+    double v = 0.28209479177387814347403972578039;  // 1/sqrt(4 pi)
+    int e = 0;
+    mant[q] = v;
+    expo[q] = 0;
+    for (int m = 1; m <= lmax; ++m) {
+        v *= -st * sqrt((2.0 * m + 1.0) / (2.0 * m));
+        if (fabs(v) < 0x1p-256) {
+            v = ldexp(v, 256);
+            e -= 256;
+        }
+        mant[(size_t)m * nq + q] = v;
+        expo[(size_t)m * nq + q] = e;
+    }
+}
+
+// Walk the recurrence up from l = m until |lambda_lm| >= 2^kSkipLog2; record
+// that l and mu_{l-1}, mu_l (true scale).  kNever if it is not reached by lmax.
+__global__ void k_seed_up(int lmax, int nq, const double* __restrict__ xs,
+                          const double* __restrict__ A, const double* __restrict__ g,
+                          const double* __restrict__ mant, const int* __restrict__ expo,
+                          int* __restrict__ ls_out, double* __restrict__ s0_out,
+                          double* __restrict__ s1_out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (q >= nq) return;
+    const size_t o = (size_t)m * nq + q;
+    const double x = xs[q];
+    const long long base = alm_base(m, lmax);
+    const double thr = ldexp(1.0, kSkipLog2);
+    double cur = mant[o], prev = 0.0;
+    int e = expo[o];
+    int l = m;
+    if (!(ldexp(fabs(g[base + l] * cur), e) >= thr)) {
+        for (l = m + 1; l <= lmax; ++l) {
+            const double nx = fma(A[base + l] * x, cur, -prev);
+            prev = cur;
+            cur = nx;
+            if (fabs(cur) > 0x1p256) {
+                cur = ldexp(cur, -256);
+                prev = ldexp(prev, -256);
+                e += 256;
+            }
+            if (ldexp(fabs(g[base + l] * cur), e) >= thr) break;
+        }
+    }
+    if (l > lmax) {
+        ls_out[o] = kNever;
+        s0_out[o] = 0.0;
+        s1_out[o] = 0.0;
+    } else {
+        ls_out[o] = l;
+        s0_out[o] = ldexp(prev, e);
+        s1_out[o] = ldexp(cur, e);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// synthesis
+// ---------------------------------------------------------------------------
+struct SynArgs {
+    const double* x;
+    const int* ls;
+    const double* s0;
+    const double* s1;
+    const double* A;
+    const double2* ap;
+    double2* spec;
+    const int* ell;
+    int lmax, nq;
+};
+
+// One even/odd pair of recurrence steps (l even offset from m, l+1 odd) for
+// the K rings of a lane.  With INJ the lanes whose start is l or l+1 load
+// their stored (mu_{ls-1}, mu_ls) there.
+template <int K, bool INJ>
+__device__ __forceinline__ void syn_pair(int l, bool odd_live, const double* __restrict__ A,
+                                         const double2* __restrict__ ap, const double (&x)[K],
+                                         double (&p1)[K], double (&p2)[K], double (&er)[K],
+                                         double (&ei)[K], double (&orr)[K], double (&oi)[K],
+                                         const int (&ls)[K], const double (&s0)[K],
+                                         const double (&s1)[K]) {
+    const double Ae = A[l], Ao = A[l + 1];
+    const double2 ce = ap[l];
+    double2 co = ap[l + 1];
+    if (!odd_live) co = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        double ue = fma(Ae * x[t], p1[t], -p2[t]);
+        if (INJ && l == ls[t]) {
+            ue = s1[t];
+            p1[t] = s0[t];
+        }
+        er[t] = fma(ue, ce.x, er[t]);
+        ei[t] = fma(ue, ce.y, ei[t]);
+        double uo = fma(Ao * x[t], ue, -p1[t]);
+        if (INJ && l + 1 == ls[t]) {
+            uo = s1[t];
+            ue = s0[t];
+        }
+        orr[t] = fma(uo, co.x, orr[t]);
+        oi[t] = fma(uo, co.y, oi[t]);
+        p2[t] = ue;
+        p1[t] = uo;
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(64) void k_leg_syn(SynArgs a) {
+    const int m = blockIdx.y;
+    const int ell = *a.ell;
+    if (m > ell) return;
+    const int lane = threadIdx.x;
+    const int nq = a.nq;
+    const int q0 = blockIdx.x * (64 * K) + lane;
+    const size_t mo = (size_t)m * nq;
+    double x[K], p1[K], p2[K], er[K], ei[K], orr[K], oi[K], s0[K], s1[K];
+    int ls[K];
+    int lo = kNever, hi = -1;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        const int q = q0 + 64 * t;
+        const bool v = q < nq;
+        x[t] = v ? a.x[q] : 0.0;
+        int l0 = v ? a.ls[mo + q] : kNever;
+        if (l0 > ell) l0 = kNever;
+        ls[t] = l0;
+        const bool act = l0 != kNever;
+        s0[t] = act ? a.s0[mo + q] : 0.0;
+        s1[t] = act ? a.s1[mo + q] : 0.0;
+        lo = min(lo, l0);
+        if (act) hi = max(hi, l0);
+        p1[t] = p2[t] = er[t] = ei[t] = orr[t] = oi[t] = 0.0;
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if (lo <= ell) {
+        const long long base = alm_base(m, a.lmax);
+        const double* A = a.A + base;
+        const double2* ap = a.ap + base;
+        int l = m + ((lo - m) & ~1);
+        for (; l <= hi; l += 2)
+            syn_pair<K, true>(l, l + 1 <= ell, A, ap, x, p1, p2, er, ei, orr, oi, ls, s0, s1);
+        for (; l + 15 <= ell; l += 16) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                syn_pair<K, false>(l + 2 * j, true, A, ap, x, p1, p2, er, ei, orr, oi, ls, s0, s1);
+        }
+        for (; l <= ell; l += 2)
+            syn_pair<K, false>(l, l + 1 <= ell, A, ap, x, p1, p2, er, ei, orr, oi, ls, s0, s1);
+    }
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        const int q = q0 + 64 * t;
+        if (q < nq) {
+            a.spec[(mo + q) * 2 + 0] = make_double2(er[t] + orr[t], ei[t] + oi[t]);
+            a.spec[(mo + q) * 2 + 1] = make_double2(er[t] - orr[t], ei[t] - oi[t]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// analysis
+// ---------------------------------------------------------------------------
+struct AnaArgs {
+    const double* x;
+    const int* ls;
+    const double* s0;
+    const double* s1;
+    const double* A;
+    const double2* spec;
+    double2* part;
+    size_t part_stride;
+    const int* ell;
+    int lmax, nq;
+};
+
+// Eight even/odd pairs (16 l) accumulating the lane's K rings into acc[].
+template <int K, bool INJ>
+__device__ __forceinline__ void ana_block(int l0, const double* __restrict__ A,
+                                          const double (&x)[K], double (&p1)[K], double (&p2)[K],
+                                          const double (&gpr)[K], const double (&gpi)[K],
+                                          const double (&gmr)[K], const double (&gmi)[K],
+                                          const int (&ls)[K], const double (&s0)[K],
+                                          const double (&s1)[K], double (&accr)[kAnaB],
+                                          double (&acci)[kAnaB]) {
+#pragma unroll
+    for (int j = 0; j < kAnaB / 2; ++j) {
+        const int l = l0 + 2 * j;
+        const double Ae = A[l], Ao = A[l + 1];
+        double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            double ue = fma(Ae * x[t], p1[t], -p2[t]);
+            if (INJ && l == ls[t]) {
+                ue = s1[t];
+                p1[t] = s0[t];
+            }
+            er = fma(ue, gpr[t], er);
+            ei = fma(ue, gpi[t], ei);
+            double uo = fma(Ao * x[t], ue, -p1[t]);
+            if (INJ && l + 1 == ls[t]) {
+                uo = s1[t];
+                ue = s0[t];
+            }
+            orr = fma(uo, gmr[t], orr);
+            oi = fma(uo, gmi[t], oi);
+            p2[t] = ue;
+            p1[t] = uo;
+        }
+        accr[2 * j] = er;
+        acci[2 * j] = ei;
+        accr[2 * j + 1] = orr;
+        acci[2 * j + 1] = oi;
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(64) void k_leg_ana(AnaArgs a) {
+    __shared__ double2 red[kAnaB][65];
+    const int m = blockIdx.y;
+    const int ell = *a.ell;
+    if (m > ell) return;
+    const int lane = threadIdx.x;
+    const int nq = a.nq;
+    const int q0 = blockIdx.x * (64 * K) + lane;
+    const size_t mo = (size_t)m * nq;
+    double x[K], p1[K], p2[K], gpr[K], gpi[K], gmr[K], gmi[K], s0[K], s1[K];
+    int ls[K];
+    int lo = kNever, hi = -1;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        const int q = q0 + 64 * t;
+        const bool v = q < nq;
+        x[t] = v ? a.x[q] : 0.0;
+        int l0 = v ? a.ls[mo + q] : kNever;
+        if (l0 > ell) l0 = kNever;
+        ls[t] = l0;
+        const bool act = l0 != kNever;
+        s0[t] = act ? a.s0[mo + q] : 0.0;
+        s1[t] = act ? a.s1[mo + q] : 0.0;
+        double2 gn = make_double2(0.0, 0.0), gs = make_double2(0.0, 0.0);
+        if (act) {
+            gn = a.spec[(mo + q) * 2 + 0];
+            gs = a.spec[(mo + q) * 2 + 1];
+        }
+        gpr[t] = gn.x + gs.x;
+        gpi[t] = gn.y + gs.y;
+        gmr[t] = gn.x - gs.x;
+        gmi[t] = gn.y - gs.y;
+        lo = min(lo, l0);
+        if (act) hi = max(hi, l0);
+        p1[t] = p2[t] = 0.0;
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    const long long base = alm_base(m, a.lmax);
+    double2* out = a.part + blockIdx.x * a.part_stride + base;
+    if (lo > ell) {
+        for (int l = m + lane; l <= ell; l += 64) out[l] = make_double2(0.0, 0.0);
+        return;
+    }
+    const double* A = a.A + base;
+    const int L0 = m + ((lo - m) & ~1);
+    for (int l = m + lane; l < L0; l += 64) out[l] = make_double2(0.0, 0.0);
+    const int rb = lane >> 2, rp = lane & 3;
+    for (int l0 = L0; l0 <= ell; l0 += kAnaB) {
+        double accr[kAnaB], acci[kAnaB];
+        if (l0 <= hi)
+            ana_block<K, true>(l0, A, x, p1, p2, gpr, gpi, gmr, gmi, ls, s0, s1, accr, acci);
+        else
+            ana_block<K, false>(l0, A, x, p1, p2, gpr, gpi, gmr, gmi, ls, s0, s1, accr, acci);
+#pragma unroll
+        for (int b = 0; b < kAnaB; ++b) red[b][lane] = make_double2(accr[b], acci[b]);
+        __syncthreads();
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const double2 v = red[rb][rp * 16 + i];
+            sr += v.x;
+            si += v.y;
+        }
+        sr += __shfl_xor(sr, 1);
+        si += __shfl_xor(si, 1);
+        sr += __shfl_xor(sr, 2);
+        si += __shfl_xor(si, 2);
+        __syncthreads();
+        if (rp == 0 && l0 + rb <= ell) out[l0 + rb] = make_double2(sr, si);
+    }
+}
+
+}  // namespace
+
+dmwf_status launch_seeds(dmwf_plan* p, hipStream_t s) {
+    const size_t cnt = (size_t)(p->lmax + 1) * p->nq;
+    double* mant = nullptr;
+    int* expo = nullptr;
+    DMWF_HIP(hipMalloc(&mant, cnt * sizeof(double)));
+    DMWF_HIP(hipMalloc(&expo, cnt * sizeof(int)));
+    {
+        ProfScope ps(p, s, PROF_SEED);
+        hipLaunchKernelGGL(k_seed_mm, dim3((p->nq + 63) / 64), dim3(64), 0, s, p->lmax, p->nq,
+                           p->d_sint, mant, expo);
+        hipLaunchKernelGGL(k_seed_up, dim3((p->nq + 63) / 64, p->lmax + 1), dim3(64), 0, s,
+                           p->lmax, p->nq, p->d_x, p->d_A, p->d_g, mant, expo, p->d_ls, p->d_s0,
+                           p->d_s1);
+    }
+    DMWF_HIP(hipGetLastError());
+    DMWF_HIP(hipStreamSynchronize(s));
+    DMWF_HIP(hipFree(mant));
+    DMWF_HIP(hipFree(expo));
+    return DMWF_OK;
+}
+
+dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const int* ell_dev,
+                           hipStream_t s) {
+    SynArgs a{p->d_x, p->d_ls, p->d_s0, p->d_s1, p->d_A, ap, spec, ell_dev, p->lmax, p->nq};
+    ProfScope ps(p, s, PROF_LEG_SYN);
+    hipLaunchKernelGGL(k_leg_syn<kSynK>, dim3(p->nchunk_syn, p->lmax + 1), dim3(64), 0, s, a);
+    DMWF_HIP(hipGetLastError());
+    return DMWF_OK;
+}
+
+dmwf_status launch_leg_ana(dmwf_plan* p, const double2* spec, double2* part, const int* ell_dev,
+                           hipStream_t s) {
+    AnaArgs a{p->d_x,  p->d_ls, p->d_s0, p->d_s1, p->d_A, spec, part,
+              (size_t)p->nalm + kTablePad, ell_dev, p->lmax, p->nq};
+    ProfScope ps(p, s, PROF_LEG_ANA);
+    hipLaunchKernelGGL(k_leg_ana<kAnaK>, dim3(p->nchunk_ana, p->lmax + 1), dim3(64), 0, s, a);
+    DMWF_HIP(hipGetLastError());
+    return DMWF_OK;
+}
+
+}  // namespace dmwf

@@ -1,0 +1,232 @@
+"""Python binding of the C ABI in include/dmwf.h (argument marshalling only).
+
+Every computation runs in the HIP library libdmwf.so built next to this file;
+there is no fallback.  Arrays are torch tensors on the GPU (float64,
+contiguous); the library enqueues its work on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdmwf.so")
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "workspace", 3: "HIP error", 4: "not converged",
+          5: "non-finite", 6: "unsupported", 7: "out of memory"}
+OK, ERR_INVALID_ARG, ERR_WORKSPACE, ERR_HIP, ERR_NOT_CONVERGED, ERR_NONFINITE, ERR_UNSUPPORTED, \
+    ERR_OOM = range(8)
+
+
+class DmwfError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({msg})")
+        self.status = status
+
+
+class _PlanDesc(ctypes.Structure):
+    _fields_ = [("nside", ctypes.c_int), ("lmax", ctypes.c_int), ("nmaps", ctypes.c_int),
+                ("precision", ctypes.c_int)]
+
+
+class _Schedule(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("mu0", ctypes.c_double),
+                ("eps_final", ctypes.c_double), ("eps_coarse", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("start_final", ctypes.c_int),
+                ("replay_iters", ctypes.POINTER(ctypes.c_int)), ("n_replay", ctypes.c_int),
+                ("want_residual", ctypes.c_int)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int), ("n_iter", ctypes.c_int), ("alpha", ctypes.c_double),
+                ("final_cauchy", ctypes.c_double), ("wf_residual", ctypes.c_double),
+                ("cap_levels", ctypes.c_int), ("iters_per_level", ctypes.POINTER(ctypes.c_int)),
+                ("xi_per_level", ctypes.POINTER(ctypes.c_double)),
+                ("lmax_per_level", ctypes.POINTER(ctypes.c_int))]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libdmwf.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(or python paper_1702_08852_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, sz, ci, cd = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_double
+    lib.dmwf_plan_create.argtypes = [ctypes.POINTER(_PlanDesc), ctypes.POINTER(vp)]
+    lib.dmwf_plan_destroy.argtypes = [vp]
+    lib.dmwf_plan_destroy.restype = None
+    lib.dmwf_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.dmwf_alm2map.argtypes = [vp, vp, vp, vp, sz, vp]
+    lib.dmwf_adjoint.argtypes = [vp, vp, vp, ci, vp, sz, vp]
+    lib.dmwf_dm_iterate.argtypes = [vp, cd, cd, vp, vp, vp, vp, vp, vp, ci, vp, sz, vp]
+    lib.dmwf_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(_Schedule), vp, vp,
+                               ctypes.POINTER(_Stats), vp, sz, vp]
+    lib.dmwf_wf_residual.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(cd), vp, sz, vp]
+    lib.dmwf_profile_enable.argtypes = [vp, ci]
+    lib.dmwf_profile_read.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ctypes.c_char_p),
+                                      ctypes.POINTER(ctypes.c_long), ctypes.POINTER(cd)]
+    lib.dmwf_status_string.argtypes = [ci]
+    lib.dmwf_status_string.restype = ctypes.c_char_p
+    lib.dmwf_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str, allow=()):
+    if status != OK and status not in allow:
+        raise DmwfError(status, where, load().dmwf_last_error().decode())
+    return status
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    if t is None:
+        return None
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def n_alm(lmax: int) -> int:
+    return (lmax + 1) * (lmax + 2) // 2
+
+
+@dataclass
+class SolveStats:
+    n_levels: int
+    n_iter: int
+    alpha: float
+    final_cauchy: float
+    wf_residual: float
+    iters_per_level: list = field(default_factory=list)
+    xi_per_level: list = field(default_factory=list)
+    lmax_per_level: list = field(default_factory=list)
+    status: int = OK
+
+
+class Plan:
+    """A transform/solver plan for maps of one (nside, lmax), owning its workspace."""
+
+    def __init__(self, nside: int, lmax: int, nmaps: int = 1, device=None):
+        lib = load()
+        self.nside, self.lmax, self.nmaps = int(nside), int(lmax), int(nmaps)
+        self.npix = 12 * self.nside * self.nside
+        self.nalm = n_alm(self.lmax)
+        dev = torch.device("cuda" if device is None else device)
+        with torch.cuda.device(dev):
+            h = ctypes.c_void_p()
+            desc = _PlanDesc(self.nside, self.lmax, self.nmaps, 0)
+            _check(lib.dmwf_plan_create(ctypes.byref(desc), ctypes.byref(h)), "dmwf_plan_create")
+            self._h = h
+            nb = ctypes.c_size_t()
+            _check(lib.dmwf_workspace_bytes(self._h, ctypes.byref(nb)), "dmwf_workspace_bytes")
+            self.ws_bytes = int(nb.value)
+            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.device = dev
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().dmwf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers --
+    def _alm(self, out=None):
+        if out is None:
+            out = torch.empty((self.nmaps, self.nalm, 2) if self.nmaps > 1 else (self.nalm, 2),
+                              dtype=torch.float64, device=self.device)
+        return out
+
+    def _map(self, out=None):
+        if out is None:
+            out = torch.empty((self.nmaps, self.npix) if self.nmaps > 1 else (self.npix,),
+                              dtype=torch.float64, device=self.device)
+        return out
+
+    # -- entry points --
+    def alm2map(self, alm: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = self._map(out)
+        _check(load().dmwf_alm2map(self._h, _ptr(alm), _ptr(out), self.ws.data_ptr(),
+                                   self.ws_bytes, _stream()), "dmwf_alm2map")
+        return out
+
+    def adjoint(self, mp: torch.Tensor, scale_by_pixel_area: bool = False,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+        out = self._alm(out)
+        _check(load().dmwf_adjoint(self._h, _ptr(mp), _ptr(out), int(bool(scale_by_pixel_area)),
+                                   self.ws.data_ptr(), self.ws_bytes, _stream()), "dmwf_adjoint")
+        return out
+
+    def dm_iterate(self, xi: float, alpha: float, cl, d, ninv, alm_state, s_map, cauchy2,
+                   first: bool) -> None:
+        _check(load().dmwf_dm_iterate(self._h, float(xi), float(alpha), _ptr(cl), _ptr(d),
+                                      _ptr(ninv), _ptr(alm_state), _ptr(s_map), _ptr(cauchy2),
+                                      int(bool(first)), self.ws.data_ptr(), self.ws_bytes,
+                                      _stream()), "dmwf_dm_iterate")
+
+    def solve(self, cl, d, ninv, beta: float = 0.75, mu0: float = -1.0, eps_final: float = 1e-6,
+              eps_coarse: float = 1e-4, max_iter: int = 1_000_000, replay=None,
+              start_final: bool = False, alm: torch.Tensor | None = None,
+              out_map: torch.Tensor | None = None, want_residual: bool = False,
+              raise_on_cap: bool = False, cap_levels: int = 512):
+        alm = self._alm(alm)
+        out_map = self._map(out_map)
+        rep = None
+        if replay is not None:
+            rep = (ctypes.c_int * len(replay))(*[int(v) for v in replay])
+        sc = _Schedule(float(beta), float(mu0), float(eps_final), float(eps_coarse),
+                       int(max_iter), int(bool(start_final)),
+                       ctypes.cast(rep, ctypes.POINTER(ctypes.c_int)) if rep is not None else None,
+                       len(replay) if replay is not None else 0, int(bool(want_residual)))
+        ipl = (ctypes.c_int * cap_levels)()
+        xpl = (ctypes.c_double * cap_levels)()
+        lpl = (ctypes.c_int * cap_levels)()
+        st = _Stats(0, 0, 0.0, 0.0, -1.0, cap_levels, ipl, xpl, lpl)
+        status = load().dmwf_solve(self._h, _ptr(cl), _ptr(d), _ptr(ninv), ctypes.byref(sc),
+                                   _ptr(alm), _ptr(out_map), ctypes.byref(st),
+                                   self.ws.data_ptr(), self.ws_bytes, _stream())
+        _check(status, "dmwf_solve", allow=() if raise_on_cap else (ERR_NOT_CONVERGED,))
+        nl = min(st.n_levels, cap_levels)
+        stats = SolveStats(st.n_levels, st.n_iter, st.alpha, st.final_cauchy, st.wf_residual,
+                           list(ipl[:nl]), list(xpl[:nl]), list(lpl[:nl]), status)
+        return alm, out_map, stats
+
+    def wf_residual(self, cl, d, ninv, alm) -> float:
+        out = ctypes.c_double()
+        _check(load().dmwf_wf_residual(self._h, _ptr(cl), _ptr(d), _ptr(ninv), _ptr(alm),
+                                       ctypes.byref(out), self.ws.data_ptr(), self.ws_bytes,
+                                       _stream()), "dmwf_wf_residual")
+        return float(out.value)
+
+    def profile(self, enable: bool = True) -> None:
+        _check(load().dmwf_profile_enable(self._h, int(bool(enable))), "dmwf_profile_enable")
+
+    def profile_read(self) -> dict:
+        n = ctypes.c_int()
+        names = (ctypes.c_char_p * 16)()
+        counts = (ctypes.c_long * 16)()
+        ms = (ctypes.c_double * 16)()
+        _check(load().dmwf_profile_read(self._h, ctypes.byref(n), names, counts, ms),
+               "dmwf_profile_read")
+        return {names[i].decode(): (int(counts[i]), float(ms[i])) for i in range(n.value)}
+
+
+def status_string(status: int) -> str:
+    return load().dmwf_status_string(status).decode()
