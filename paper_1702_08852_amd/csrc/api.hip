@@ -284,6 +284,7 @@ void dmwf_plan_destroy(dmwf_plan* p) {
         (void)hipEventDestroy(e.start);
         (void)hipEventDestroy(e.stop);
     }
+    free_ring_tables(p);
     void* bufs[] = {p->d_x, p->d_sint, p->d_nph, p->d_phi0pi, p->d_start_n, p->d_start_s,
                     p->d_A, p->d_g,    p->d_ls,  p->d_s0,     p->d_s1};
     for (void* b : bufs)
@@ -316,6 +317,10 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
     }
     if (desc->precision != DMWF_FP64) {
         set_error("only DMWF_FP64 is implemented");
+        return DMWF_ERR_UNSUPPORTED;
+    }
+    if (N > 1024) {
+        set_error("nside > 1024 needs ring FFTs longer than one workgroup's LDS; not implemented");
         return DMWF_ERR_UNSUPPORTED;
     }
     dmwf_plan* p = new dmwf_plan();
@@ -420,6 +425,8 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
     }
     dmwf_status s = launch_seeds(p, nullptr);
     if (s != DMWF_OK) return fail(s);
+    s = build_ring_tables(p);
+    if (s != DMWF_OK) return fail(s);
 
     // ---- workspace layout ----
     WsLayout& w = p->ws;
@@ -474,8 +481,8 @@ dmwf_status dmwf_profile_read(dmwf_plan* p, int* n_classes, const char** names, 
         DMWF_HIP(hipEventElapsedTime(&ms, e.start, e.stop));
         if (counts) counts[e.cls] += 1;
         if (total_ms) total_ms[e.cls] += ms;
-        (void)hipEventDestroy(e.start);
-        (void)hipEventDestroy(e.stop);
+        p->event_pool.push_back(e.start);
+        p->event_pool.push_back(e.stop);
     }
     p->events.clear();
     return DMWF_OK;

@@ -86,10 +86,22 @@ struct dmwf_plan {
     int* d_ls = nullptr;    // [(lmax+1)][nq] first significant l
     double* d_s0 = nullptr; // mu at ls-1
     double* d_s1 = nullptr; // mu at ls
+    // ring FFT tables (see ring.hip)
+    int* d_ring_M = nullptr;           // per q: FFT length (n, or the Bluestein length)
+    int* d_ring_blue = nullptr;        // per q: 1 if the ring length is not a power of two
+    long long* d_ring_coff = nullptr;  // per q: offset into the chirp table
+    long long* d_ring_boff = nullptr;  // per q: offset into the filter-spectrum table
+    double2* d_twiddle = nullptr;      // e^{-2 pi i t / Mmax}, t < Mmax / 2
+    int twiddle_log = 0;               // log2 Mmax
+    double2* d_chirp = nullptr;        // e^{i pi t^2 / n}, t < n, per Bluestein ring
+    double2* d_bspec = nullptr;        // FFT_M of the chirp filter, per Bluestein ring
+    int* d_ring_class = nullptr;       // q lists of the launch classes, concatenated
+    int class_off[5] = {0, 0, 0, 0, 0};
     dmwf::WsLayout ws;
     // profiling
     bool prof = false;
     std::vector<dmwf::ProfEvent> events;
+    std::vector<hipEvent_t> event_pool;  // recorded events are returned here on read
     dmwf::RingGeom geom() const {
         return {d_x, d_sint, d_nph, d_phi0pi, d_start_n, d_start_s};
     }
@@ -109,7 +121,18 @@ void set_error(const std::string& msg);
         }                                                                       \
     } while (0)
 
-// Bracket a launch with profiling events when enabled.
+inline hipEvent_t pool_event(dmwf_plan* p) {
+    hipEvent_t e = nullptr;
+    if (!p->event_pool.empty()) {
+        e = p->event_pool.back();
+        p->event_pool.pop_back();
+    } else {
+        (void)hipEventCreate(&e);
+    }
+    return e;
+}
+
+// Bracket a launch with profiling events (recorded on the launch stream) when enabled.
 struct ProfScope {
     dmwf_plan* p;
     hipStream_t s;
@@ -117,8 +140,8 @@ struct ProfScope {
     hipEvent_t a = nullptr, b = nullptr;
     ProfScope(dmwf_plan* p_, hipStream_t s_, int c_) : p(p_), s(s_), cls(c_) {
         if (p->prof) {
-            (void)hipEventCreate(&a);
-            (void)hipEventCreate(&b);
+            a = pool_event(p);
+            b = pool_event(p);
             (void)hipEventRecord(a, s);
         }
     }
@@ -171,6 +194,9 @@ struct RingIO {
 // by the analysis (device scalars).
 dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const int* ell_syn,
                         const int* ell_ana, const RingIO& io, hipStream_t s);
-size_t ring_lds_bytes(const dmwf_plan* p);
+// Ring transform tables and launch classes; called by dmwf_plan_create.
+dmwf_status build_ring_tables(dmwf_plan* p);
+void free_ring_tables(dmwf_plan* p);
+constexpr int kRingClasses = 4;
 
 }  // namespace dmwf

@@ -1,0 +1,136 @@
+"""GPU path against the oracle at the workload sizes.
+
+Full transforms up to Nside 512; at the paper-scale Nside 1024 / lmax 2048
+(the benchmark's launch configuration) the oracle evaluates sampled rings and
+sampled m one by one, and one full iteration through the C ABI is checked
+against an oracle iteration.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import dmwf_inputs as inp
+import oracle
+from oracle import dm
+from gpu_util import device, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(nside, lmax):
+    from paper_1702_08852_amd import Plan
+    return Plan(nside, lmax, device=device())
+
+
+@pytest.mark.parametrize("nside,lmax", [(128, 256), (256, 512), (512, 1024)])
+def test_transforms_full(nside, lmax):
+    dev = device()
+    a = inp.random_alm(lmax, 7 + nside)
+    plan = _plan(nside, lmax)
+    got = plan.alm2map(to_dev(a, dev)).cpu().numpy()
+    assert rel(got, oracle.alm2map(a, nside, lmax)) < 1e-12
+    mp = inp.random_map(nside, 9 + nside)
+    got = plan.adjoint(to_dev(mp, dev)).cpu().numpy()
+    assert rel(got, oracle.adjoint(mp, nside, lmax)) < 1e-12
+
+
+RINGS_1024 = [1, 2, 3, 4, 100, 511, 512, 1023, 1024, 1025, 1500, 2047, 2048, 2049, 3000, 3071,
+              3072, 3073, 4000, 4093, 4094, 4095]
+MS_2048 = [0, 1, 2, 3, 50, 511, 512, 1000, 1023, 1024, 1500, 2000, 2046, 2047, 2048]
+
+
+def test_alm2map_nside1024_sampled_rings():
+    dev = device()
+    nside, lmax = 1024, 2048
+    a = inp.random_alm(lmax, 1024)
+    got = _plan(nside, lmax).alm2map(to_dev(a, dev)).cpu().numpy()
+    z, st, nph, p0, start = oracle.rings(nside)
+    ref = oracle.alm2map_rings(a, nside, lmax, RINGS_1024)
+    mine = np.concatenate([got[start[r - 1]:start[r - 1] + nph[r - 1]] for r in RINGS_1024])
+    assert rel(mine, ref) < 1e-12
+    o = 0
+    for r in RINGS_1024:  # every sampled ring on its own
+        n = nph[r - 1]
+        assert rel(mine[o:o + n], ref[o:o + n]) < 1e-11, r
+        o += n
+
+
+def test_adjoint_nside1024_sampled_m():
+    dev = device()
+    nside, lmax = 1024, 2048
+    mp = inp.random_map(nside, 1025)
+    got = _plan(nside, lmax).adjoint(to_dev(mp, dev)).cpu().numpy()
+    ref = oracle.adjoint_m(mp, nside, lmax, MS_2048)
+    for m, v in ref.items():
+        k0 = oracle.alm_index(m, m, lmax)
+        assert rel(got[k0:k0 + lmax - m + 1], v) < 1e-12, m
+
+
+def _problem(name, nside):
+    p = inp.make_problem(name, nside=nside)
+    T = oracle.SphereTransforms(nside, p.lmax)
+    d = p.data_map(T.synth(p.alm_true))
+    return p, T, d, p.ninv
+
+
+@pytest.mark.parametrize("level", [0, 20, -1])
+def test_dm_iterate_nside256_cfg2(level):
+    """Configuration 2 recipe (Nside 256, lmax 512): three iterations on one level."""
+    import torch
+    dev = device()
+    nside = 256
+    p, T, d, w = _problem("cfg2", nside)
+    alpha = dm.alpha_of(w)
+    sigma = 1.0 / T.omega
+    xi = dm.level_schedule(alpha, sigma, p.cl, 0.75)[level]
+    mu, f, li = dm.level_params(xi, alpha, sigma, p.cl)
+    c = dm.pixel_coeff(xi, alpha, w)
+    plan = _plan(nside, p.lmax)
+    cl_t, d_t, w_t = to_dev(p.cl, dev), to_dev(d, dev), to_dev(w, dev)
+    a_t = torch.zeros((oracle.n_alm(p.lmax), 2), dtype=torch.float64, device=dev)
+    s_t = torch.zeros(12 * nside * nside, dtype=torch.float64, device=dev)
+    c2 = torch.zeros(2, dtype=torch.float64, device=dev)
+    a = np.zeros((oracle.n_alm(p.lmax), 2))
+    r = np.where(w > 0, d, 0.0)
+    s_prev = np.zeros_like(d)
+    for it in range(3):
+        plan.dm_iterate(xi, alpha, cl_t, d_t, w_t, a_t, s_t, c2, first=(it == 0))
+        a, s, r, num, den = dm.iterate(T, a, r, f[T.ell()], c, d, s_prev)
+        s_prev = s
+        assert rel(a_t.cpu().numpy(), a) < 1e-11
+        assert rel(s_t.cpu().numpy(), s) < 1e-11
+        cc = c2.cpu().numpy()
+        assert cc[1] == pytest.approx(den, rel=1e-11)
+        assert cc[0] == pytest.approx(num, rel=1e-8, abs=1e-13 * den)
+
+
+def test_dm_iterate_nside1024_cfg3_first_iteration():
+    """Configuration 3 recipe at full size: the first iteration at the final level xi = alpha."""
+    import torch
+    dev = device()
+    nside = 1024
+    p, T, d, w = _problem("cfg3", nside)
+    assert abs(p.meta["masked_fraction"] - 0.20) < 0.005
+    alpha = dm.alpha_of(w)
+    sigma = 1.0 / T.omega
+    xi = alpha
+    mu, f, li = dm.level_params(xi, alpha, sigma, p.cl)
+    plan = _plan(nside, p.lmax)
+    cl_t, d_t, w_t = to_dev(p.cl, dev), to_dev(d, dev), to_dev(w, dev)
+    a_t = torch.zeros((oracle.n_alm(p.lmax), 2), dtype=torch.float64, device=dev)
+    s_t = torch.zeros(12 * nside * nside, dtype=torch.float64, device=dev)
+    c2 = torch.zeros(2, dtype=torch.float64, device=dev)
+    plan.dm_iterate(xi, alpha, cl_t, d_t, w_t, a_t, s_t, c2, first=True)
+    a_gpu = a_t.cpu().numpy()
+    s_gpu = s_t.cpu().numpy()
+    # oracle: a_1 = f (Omega Y^H d[w>0]) in full, s_1 = Y a_1 on sampled rings
+    r0 = np.where(w > 0, d, 0.0)
+    a1 = f[T.ell()][:, None] * (T.omega * T.adjoint(r0))
+    assert rel(a_gpu, a1) < 1e-11
+    z, st, nph, p0, start = oracle.rings(nside)
+    ref = oracle.alm2map_rings(a1, nside, p.lmax, RINGS_1024)
+    mine = np.concatenate([s_gpu[start[r - 1]:start[r - 1] + nph[r - 1]] for r in RINGS_1024])
+    assert rel(mine, ref) < 1e-11
+    cc = c2.cpu().numpy()
+    assert math.isfinite(cc[0]) and cc[0] == pytest.approx(cc[1], rel=1e-12)  # s_prev = 0
