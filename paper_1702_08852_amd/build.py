@@ -7,8 +7,8 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-BUILD = os.path.join(HERE, "_build")
-LIB = os.path.join(HERE, "libdmwf.so")
+BUILD = os.environ.get("DMWF_BUILD_DIR", os.path.join(HERE, "_build"))
+LIB = os.environ.get("DMWF_LIB_OUT", os.path.join(HERE, "libdmwf.so"))
 SOURCES = ["api.hip", "legendre.hip", "ring.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -16,7 +16,7 @@ FLAGS = [
     # no packed FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
-]
+] + os.environ.get("DMWF_EXTRA_FLAGS", "").split()
 
 
 def _compile(src: str) -> str:

@@ -226,6 +226,7 @@ struct Ws {
     double2* ap() const { return reinterpret_cast<double2*>(base + off.ap); }
     double2* aux() const { return reinterpret_cast<double2*>(base + off.aux); }
     double* cpart() const { return reinterpret_cast<double*>(base + off.cpart); }
+    int* mhi() const { return reinterpret_cast<int*>(base + off.mhi); }
     int* ell() const { return reinterpret_cast<int*>(base + off.scal); }
     int* flags() const { return reinterpret_cast<int*>(base + off.scal + 4); }
     int* ell_ana() const { return reinterpret_cast<int*>(base + off.scal + 8); }
@@ -286,7 +287,8 @@ void dmwf_plan_destroy(dmwf_plan* p) {
     }
     free_ring_tables(p);
     void* bufs[] = {p->d_x, p->d_sint, p->d_nph, p->d_phi0pi, p->d_start_n, p->d_start_s,
-                    p->d_A, p->d_g,    p->d_ls,  p->d_s0,     p->d_s1};
+                    p->d_A, p->d_g,    p->d_ls,  p->d_s0,     p->d_s1, p->d_lsmin,
+                    p->d_mhi_full};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -334,6 +336,7 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
     p->omega = 4.0 * kPi / (double)p->npix;
     p->nchunk_syn = (p->nq + 64 * kSynK - 1) / (64 * kSynK);
     p->nchunk_ana = (p->nq + 64 * kAnaK - 1) / (64 * kAnaK);
+    p->lp = (p->lmax + 1 + 3) & ~3;
     if (hipGetDevice(&p->device) != hipSuccess) {
         set_error("hipGetDevice failed");
         delete p;
@@ -418,6 +421,8 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
     }
     const size_t nseed = (size_t)(L + 1) * nq;
     if (hipMalloc(&p->d_ls, nseed * sizeof(int)) != hipSuccess ||
+        hipMalloc(&p->d_lsmin, nseed * sizeof(int)) != hipSuccess ||
+        hipMalloc(&p->d_mhi_full, nq * sizeof(int)) != hipSuccess ||
         hipMalloc(&p->d_s0, nseed * sizeof(double)) != hipSuccess ||
         hipMalloc(&p->d_s1, nseed * sizeof(double)) != hipSuccess) {
         set_error("allocation of recurrence start tables failed");
@@ -432,7 +437,7 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
     WsLayout& w = p->ws;
     size_t off = 0;
     w.spec = off;
-    off = align256(off + (size_t)(L + 1) * nq * 2 * sizeof(double2));
+    off = align256(off + (size_t)p->lp * nq * 2 * sizeof(double2));
     w.part = off;
     off = align256(off + (size_t)p->nchunk_ana * ntab * sizeof(double2));
     w.ap = off;
@@ -441,6 +446,8 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
     off = align256(off + ntab * sizeof(double2));
     w.cpart = off;
     off = align256(off + (size_t)nq * 2 * sizeof(double));
+    w.mhi = off;
+    off = align256(off + (size_t)nq * sizeof(int));
     w.scal = off;
     off = align256(off + scal_bytes(p));
     w.total = off;
@@ -515,7 +522,8 @@ dmwf_status dmwf_alm2map(dmwf_plan* p, const double* alm, double* map, void* ws,
         if (st != DMWF_OK) return st;
         RingIO io{};
         io.map_out = mp;
-        st = launch_ring(p, RING_SYN, W.spec(), W.ell(), W.ell(), io, s);
+        st = launch_ring(p, RING_SYN, W.spec(), W.ell(), W.ell(), p->d_mhi_full, p->d_mhi_full, io,
+                         s);
         if (st != DMWF_OK) return st;
     }
     return DMWF_OK;
@@ -540,7 +548,8 @@ dmwf_status dmwf_adjoint(dmwf_plan* p, const double* map, double* alm, int scale
         }
         RingIO io{};
         io.map_in = mp;
-        st = launch_ring(p, RING_ANA, W.spec(), W.ell(), W.ell(), io, s);
+        st = launch_ring(p, RING_ANA, W.spec(), W.ell(), W.ell(), p->d_mhi_full, p->d_mhi_full, io,
+                         s);
         if (st != DMWF_OK) return st;
         st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), s);
         if (st != DMWF_OK) return st;
@@ -564,7 +573,7 @@ namespace {
 // step from the residual spectrum in the workspace, synthesis, pixel step.
 dmwf_status iterate_body(dmwf_plan* p, const Ws& W, double xi, double alpha, double mu,
                          const double* cl, const double* d, const double* w, double2* a,
-                         double* s_map, int first_pix, hipStream_t s) {
+                         double* s_map, int first_pix, const int* mhi_ana, hipStream_t s) {
     dmwf_status st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), s);
     if (st != DMWF_OK) return st;
     {
@@ -584,7 +593,7 @@ dmwf_status iterate_body(dmwf_plan* p, const Ws& W, double xi, double alpha, dou
     io.xi = xi;
     io.alpha = alpha;
     io.first = first_pix;
-    st = launch_ring(p, RING_ITER, W.spec(), W.ell(), W.ell_ana(), io, s);
+    st = launch_ring(p, RING_ITER, W.spec(), W.ell(), W.ell_ana(), W.mhi(), mhi_ana, io, s);
     if (st != DMWF_OK) return st;
     {
         ProfScope ps(p, s, PROF_REDUCE);
@@ -609,14 +618,16 @@ dmwf_status residual_map(dmwf_plan* p, const Ws& W, const double* cl, const doub
     RingIO io{};
     io.d = d;
     io.w = w;
-    st = launch_ring(p, RING_SYN_WRES, W.spec(), W.ell(), W.ell(), io, s);
+    st = launch_ring(p, RING_SYN_WRES, W.spec(), W.ell(), W.ell(), p->d_mhi_full, p->d_mhi_full, io,
+                     s);
     if (st != DMWF_OK) return st;
     st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), s);
     if (st != DMWF_OK) return st;
     const size_t stride = (size_t)p->nalm + kTablePad;
     hipLaunchKernelGGL(k_adj_final, alm_grid(p->lmax, 256), dim3(256), 0, s, W.part(),
                        p->nchunk_ana, stride, p->d_g, W.ap(), 1.0, p->lmax);
-    st = launch_ring(p, RING_ANA_WD, W.spec(), W.ell(), W.ell(), io, s);
+    st = launch_ring(p, RING_ANA_WD, W.spec(), W.ell(), W.ell(), p->d_mhi_full, p->d_mhi_full, io,
+                     s);
     if (st != DMWF_OK) return st;
     st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), s);
     if (st != DMWF_OK) return st;
@@ -664,15 +675,18 @@ dmwf_status dmwf_dm_iterate(dmwf_plan* p, double xi, double alpha, const double*
         hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell_ana(), p->lmax);
     }
     DMWF_HIP(hipGetLastError());
+    st = launch_mhi(p, W.ell(), W.mhi(), s);
+    if (st != DMWF_OK) return st;
     if (first) {
         RingIO io{};
         io.d = d;
         io.w = ninv;
-        st = launch_ring(p, RING_ANA_FIRST, W.spec(), W.ell_ana(), W.ell_ana(), io, s);
+        st = launch_ring(p, RING_ANA_FIRST, W.spec(), W.ell_ana(), W.ell_ana(), p->d_mhi_full,
+                         p->d_mhi_full, io, s);
         if (st != DMWF_OK) return st;
     }
     st = iterate_body(p, W, xi, alpha, mu, cl, d, ninv, reinterpret_cast<double2*>(alm_state),
-                      s_map, first ? 1 : 0, s);
+                      s_map, first ? 1 : 0, p->d_mhi_full, s);
     if (st != DMWF_OK) return st;
     DMWF_HIP(hipMemcpyAsync(cauchy2, W.out2(), 2 * sizeof(double), hipMemcpyDeviceToDevice, s));
     return DMWF_OK;
@@ -788,7 +802,8 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
             if (st != DMWF_OK) return st;
             RingIO io{};
             io.map_out = smap;
-            st = launch_ring(p, RING_SYN, W.spec(), W.ell(), W.ell(), io, s);
+            st = launch_ring(p, RING_SYN, W.spec(), W.ell(), W.ell(), p->d_mhi_full, p->d_mhi_full,
+                             io, s);
             if (st != DMWF_OK) return st;
             io = RingIO{};
             io.map_in = smap;
@@ -796,7 +811,8 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
             io.w = w;
             io.xi = alpha;
             io.alpha = alpha;
-            st = launch_ring(p, RING_ANA_CRES, W.spec(), W.ell(), W.ell(), io, s);
+            st = launch_ring(p, RING_ANA_CRES, W.spec(), W.ell(), W.ell(), p->d_mhi_full,
+                             p->d_mhi_full, io, s);
             if (st != DMWF_OK) return st;
         } else {
             {
@@ -807,7 +823,8 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
             RingIO io{};
             io.d = d;
             io.w = w;
-            st = launch_ring(p, RING_ANA_FIRST, W.spec(), W.ell(), W.ell(), io, s);
+            st = launch_ring(p, RING_ANA_FIRST, W.spec(), W.ell(), W.ell(), p->d_mhi_full,
+                             p->d_mhi_full, io, s);
             if (st != DMWF_OK) return st;
             first_pix = 1;
         }
@@ -831,13 +848,15 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
                     ProfScope ps(p, s, PROF_MISC);
                     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell(), ell);
                 }
+                st = launch_mhi(p, W.ell(), W.mhi(), s);
+                if (st != DMWF_OK) return st;
                 RingIO io{};
                 io.map_in = smap;
                 io.d = d;
                 io.w = w;
                 io.xi = xis[lev - 1];
                 io.alpha = alpha;
-                st = launch_ring(p, RING_ANA_CRES, W.spec(), W.ell(), W.ell(), io, s);
+                st = launch_ring(p, RING_ANA_CRES, W.spec(), W.ell(), W.ell(), W.mhi(), W.mhi(), io, s);
                 if (st != DMWF_OK) return st;
             }
             {
@@ -845,11 +864,13 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
                 hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell(), ell);
                 hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell_ana(), ell);
             }
+            st = launch_mhi(p, W.ell(), W.mhi(), s);
+            if (st != DMWF_OK) return st;
             ell_prev = ell;
             const double eps = xi <= alpha ? sc->eps_final : sc->eps_coarse;
             int it = 0;
             while (true) {
-                st = iterate_body(p, W, xi, alpha, mu, cl, d, w, a, smap, first_pix, s);
+                st = iterate_body(p, W, xi, alpha, mu, cl, d, w, a, smap, first_pix, W.mhi(), s);
                 if (st != DMWF_OK) return st;
                 first_pix = 0;
                 DMWF_HIP(hipMemcpyAsync(h2, W.out2(), sizeof(h2), hipMemcpyDeviceToHost, s));

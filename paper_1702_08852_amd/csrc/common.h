@@ -13,8 +13,19 @@
 namespace dmwf {
 
 // Rings per lane in the Legendre kernels: a wave covers 64*K ring pairs.
-constexpr int kSynK = 4;
-constexpr int kAnaK = 4;
+#ifndef DMWF_SYN_K
+#define DMWF_SYN_K 4
+#endif
+#ifndef DMWF_ANA_K
+#define DMWF_ANA_K 4
+#endif
+// Waves per Legendre workgroup, each on its own m (consecutive m share a CU).
+#ifndef DMWF_LEG_WAVES
+#define DMWF_LEG_WAVES 4
+#endif
+constexpr int kSynK = DMWF_SYN_K;
+constexpr int kAnaK = DMWF_ANA_K;
+constexpr int kLegWaves = DMWF_LEG_WAVES;
 // l values per analysis reduction block.
 constexpr int kAnaB = 16;
 // Padding (entries) after the per-(l,m) tables so that look-ahead reads of
@@ -58,11 +69,12 @@ struct RingGeom {
 
 // Workspace layout (byte offsets from the workspace base).
 struct WsLayout {
-    size_t spec;    // complex [(lmax+1)][nq][2]: ring Fourier coefficients F_m / G_m
+    size_t spec;    // complex [nq][lp][2]: ring Fourier coefficients F_m / G_m, ring-major
     size_t part;    // complex [nchunk_ana][n_alm + pad]: analysis partial sums
     size_t ap;      // complex [n_alm + pad]: g-scaled a_lm for the synthesis
     size_t aux;     // complex [n_alm + pad]: second a_lm-sized buffer
     size_t cpart;   // double  [nq][2]: Cauchy partial sums per ring pair
+    size_t mhi;     // int     [nq]: per ring pair, the largest m carried at the current l_iter
     size_t scal;    // small scalars: ints and doubles
     size_t total;
 };
@@ -73,6 +85,7 @@ struct dmwf_plan {
     int nside, lmax, nmaps, nq, nrings, device;
     long long npix, nalm;
     int nchunk_ana, nchunk_syn;
+    int lp;        // m-row length of the ring-major F/G buffer, lmax+1 rounded up to 4
     double omega;  // 4 pi / Npix
     // device tables
     double* d_x = nullptr;
@@ -84,6 +97,8 @@ struct dmwf_plan {
     double* d_A = nullptr;  // recurrence multipliers A_lm, m-major, + pad
     double* d_g = nullptr;  // scale g_lm with lambda_lm = g_lm mu_lm, + pad
     int* d_ls = nullptr;    // [(lmax+1)][nq] first significant l
+    int* d_lsmin = nullptr; // [nq][(lmax+1)] min over m' >= m of d_ls (non-decreasing in m)
+    int* d_mhi_full = nullptr; // [nq] largest m with d_lsmin <= lmax, or -1
     double* d_s0 = nullptr; // mu at ls-1
     double* d_s1 = nullptr; // mu at ls
     // ring FFT tables (see ring.hip)
@@ -191,9 +206,14 @@ struct RingIO {
     int first;              // RING_ITER: s_prev taken as 0
 };
 // ell_syn bounds the m of F used by the synthesis, ell_ana the m of G written
-// by the analysis (device scalars).
+// by the analysis (device scalars); mhi_syn / mhi_ana are the per-ring-pair
+// bounds for the same band limits (beyond them every lambda_lm is skipped, so
+// F is zero and G is never read).
 dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const int* ell_syn,
-                        const int* ell_ana, const RingIO& io, hipStream_t s);
+                        const int* ell_ana, const int* mhi_syn, const int* mhi_ana,
+                        const RingIO& io, hipStream_t s);
+// mhi[q] = largest m <= *ell_dev whose recurrence start is <= *ell_dev (-1 if none).
+dmwf_status launch_mhi(dmwf_plan* p, const int* ell_dev, int* mhi, hipStream_t s);
 // Ring transform tables and launch classes; called by dmwf_plan_create.
 dmwf_status build_ring_tables(dmwf_plan* p);
 void free_ring_tables(dmwf_plan* p);

@@ -106,6 +106,41 @@ __global__ void k_seed_up(int lmax, int nq, const double* __restrict__ xs,
     }
 }
 
+// Suffix minimum over m of the recurrence start, stored per ring pair:
+// lsmin[q][m] = min_{m' >= m} ls[m'][q].  Non-decreasing in m by construction.
+__global__ void k_lsmin(int lmax, int nq, const int* __restrict__ ls, int* __restrict__ lsmin) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    int run = kNever;
+    for (int m = lmax; m >= 0; --m) {
+        run = min(run, ls[(size_t)m * nq + q]);
+        lsmin[(size_t)q * (lmax + 1) + m] = run;
+    }
+}
+
+// mhi[q] = largest m <= ell with lsmin[q][m] <= ell, or -1.  Every m above it
+// has every start beyond ell, so its lambda_lm are all skipped at this band
+// limit.  Binary search on the non-decreasing lsmin.
+__global__ void k_mhi(int lmax, int nq, const int* __restrict__ lsmin, const int* ell_dev,
+                      int ell_val, int* __restrict__ mhi) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const int ell = ell_dev ? *ell_dev : ell_val;
+    const int* row = lsmin + (size_t)q * (lmax + 1);
+    int hi = min(ell, lmax);
+    if (hi < 0 || row[0] > ell) {
+        mhi[q] = -1;
+        return;
+    }
+    int lo = 0;  // row[lo] <= ell
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row[mid] <= ell) lo = mid;
+        else hi = mid - 1;
+    }
+    mhi[q] = lo;
+}
+
 // ---------------------------------------------------------------------------
 // synthesis
 // ---------------------------------------------------------------------------
@@ -118,7 +153,7 @@ struct SynArgs {
     const double2* ap;
     double2* spec;
     const int* ell;
-    int lmax, nq;
+    int lmax, nq, lp;
 };
 
 // One even/odd pair of recurrence steps (l even offset from m, l+1 odd) for
@@ -157,11 +192,19 @@ __device__ __forceinline__ void syn_pair(int l, bool odd_live, const double* __r
 }
 
 template <int K>
-__global__ __launch_bounds__(64) void k_leg_syn(SynArgs a) {
-    const int m = blockIdx.y;
+__global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn(SynArgs a) {
+    // The waves of a workgroup take consecutive m of the same ring chunk; their
+    // results meet in LDS and leave as whole 128-byte segments of the
+    // ring-major rows of F.
+    __shared__ double2 stage[K][64][kLegWaves][2];
+    const int w = threadIdx.x >> 6;
+    // wave-uniform; readfirstlane lets the compiler use scalar loads for the
+    // per-(l, m) coefficients
+    const int m = __builtin_amdgcn_readfirstlane(blockIdx.y * kLegWaves + w);
     const int ell = *a.ell;
-    if (m > ell) return;
-    const int lane = threadIdx.x;
+    if (blockIdx.y * kLegWaves > ell) return;  // whole workgroup above the band limit
+    const bool live = m <= ell;
+    const int lane = threadIdx.x & 63;
     const int nq = a.nq;
     const int q0 = blockIdx.x * (64 * K) + lane;
     const size_t mo = (size_t)m * nq;
@@ -171,7 +214,7 @@ __global__ __launch_bounds__(64) void k_leg_syn(SynArgs a) {
 #pragma unroll
     for (int t = 0; t < K; ++t) {
         const int q = q0 + 64 * t;
-        const bool v = q < nq;
+        const bool v = live && q < nq;
         x[t] = v ? a.x[q] : 0.0;
         int l0 = v ? a.ls[mo + q] : kNever;
         if (l0 > ell) l0 = kNever;
@@ -183,8 +226,10 @@ __global__ __launch_bounds__(64) void k_leg_syn(SynArgs a) {
         if (act) hi = max(hi, l0);
         p1[t] = p2[t] = er[t] = ei[t] = orr[t] = oi[t] = 0.0;
     }
-    lo = wave_min(lo);
-    hi = wave_max(hi);
+    // uniform across the wave after the reduction; say so, so that the
+    // per-l coefficient loads below become scalar loads
+    lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
+    hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
     if (lo <= ell) {
         const long long base = alm_base(m, a.lmax);
         const double* A = a.A + base;
@@ -202,11 +247,18 @@ __global__ __launch_bounds__(64) void k_leg_syn(SynArgs a) {
     }
 #pragma unroll
     for (int t = 0; t < K; ++t) {
-        const int q = q0 + 64 * t;
-        if (q < nq) {
-            a.spec[(mo + q) * 2 + 0] = make_double2(er[t] + orr[t], ei[t] + oi[t]);
-            a.spec[(mo + q) * 2 + 1] = make_double2(er[t] - orr[t], ei[t] - oi[t]);
-        }
+        stage[t][lane][w][0] = make_double2(er[t] + orr[t], ei[t] + oi[t]);
+        stage[t][lane][w][1] = make_double2(er[t] - orr[t], ei[t] - oi[t]);
+    }
+    __syncthreads();
+    constexpr int kSlots = kLegWaves * 2;
+    const int m0 = blockIdx.y * kLegWaves;
+    for (int idx = threadIdx.x; idx < K * 64 * kSlots; idx += 64 * kLegWaves) {
+        const int slot = idx % kSlots, rr = idx / kSlots;
+        const int q = blockIdx.x * (64 * K) + rr;
+        const int mm = m0 + (slot >> 1);
+        if (q < nq && mm <= ell)
+            a.spec[((size_t)q * a.lp + mm) * 2 + (slot & 1)] = stage[rr >> 6][rr & 63][slot >> 1][slot & 1];
     }
 }
 
@@ -223,7 +275,7 @@ struct AnaArgs {
     double2* part;
     size_t part_stride;
     const int* ell;
-    int lmax, nq;
+    int lmax, nq, lp;
 };
 
 // Eight even/odd pairs (16 l) accumulating the lane's K rings into acc[].
@@ -266,13 +318,22 @@ __device__ __forceinline__ void ana_block(int l0, const double* __restrict__ A,
     }
 }
 
+// Orders this wave's LDS writes before its later LDS reads (and reads before
+// later writes); the other waves of the workgroup use their own LDS region.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int K>
-__global__ __launch_bounds__(64) void k_leg_ana(AnaArgs a) {
-    __shared__ double2 red[kAnaB][65];
-    const int m = blockIdx.y;
+__global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
+    __shared__ double2 red_all[kLegWaves][kAnaB][65];
+    const int w = threadIdx.x >> 6;
+    const int m = __builtin_amdgcn_readfirstlane(blockIdx.y * kLegWaves + w);
     const int ell = *a.ell;
     if (m > ell) return;
-    const int lane = threadIdx.x;
+    double2 (*red)[65] = red_all[w];
+    const int lane = threadIdx.x & 63;
     const int nq = a.nq;
     const int q0 = blockIdx.x * (64 * K) + lane;
     const size_t mo = (size_t)m * nq;
@@ -292,8 +353,9 @@ __global__ __launch_bounds__(64) void k_leg_ana(AnaArgs a) {
         s1[t] = act ? a.s1[mo + q] : 0.0;
         double2 gn = make_double2(0.0, 0.0), gs = make_double2(0.0, 0.0);
         if (act) {
-            gn = a.spec[(mo + q) * 2 + 0];
-            gs = a.spec[(mo + q) * 2 + 1];
+            const double2* g = a.spec + ((size_t)q * a.lp + m) * 2;
+            gn = g[0];
+            gs = g[1];
         }
         gpr[t] = gn.x + gs.x;
         gpi[t] = gn.y + gs.y;
@@ -303,8 +365,10 @@ __global__ __launch_bounds__(64) void k_leg_ana(AnaArgs a) {
         if (act) hi = max(hi, l0);
         p1[t] = p2[t] = 0.0;
     }
-    lo = wave_min(lo);
-    hi = wave_max(hi);
+    // uniform across the wave after the reduction; say so, so that the
+    // per-l coefficient loads below become scalar loads
+    lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
+    hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
     const long long base = alm_base(m, a.lmax);
     double2* out = a.part + blockIdx.x * a.part_stride + base;
     if (lo > ell) {
@@ -323,7 +387,7 @@ __global__ __launch_bounds__(64) void k_leg_ana(AnaArgs a) {
             ana_block<K, false>(l0, A, x, p1, p2, gpr, gpi, gmr, gmi, ls, s0, s1, accr, acci);
 #pragma unroll
         for (int b = 0; b < kAnaB; ++b) red[b][lane] = make_double2(accr[b], acci[b]);
-        __syncthreads();
+        wave_lds_sync();
         double sr = 0.0, si = 0.0;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
@@ -335,7 +399,7 @@ __global__ __launch_bounds__(64) void k_leg_ana(AnaArgs a) {
         si += __shfl_xor(si, 1);
         sr += __shfl_xor(sr, 2);
         si += __shfl_xor(si, 2);
-        __syncthreads();
+        wave_lds_sync();
         if (rp == 0 && l0 + rb <= ell) out[l0 + rb] = make_double2(sr, si);
     }
 }
@@ -356,6 +420,10 @@ dmwf_status launch_seeds(dmwf_plan* p, hipStream_t s) {
                            p->lmax, p->nq, p->d_x, p->d_A, p->d_g, mant, expo, p->d_ls, p->d_s0,
                            p->d_s1);
     }
+    hipLaunchKernelGGL(k_lsmin, dim3((p->nq + 63) / 64), dim3(64), 0, s, p->lmax, p->nq, p->d_ls,
+                       p->d_lsmin);
+    hipLaunchKernelGGL(k_mhi, dim3((p->nq + 63) / 64), dim3(64), 0, s, p->lmax, p->nq, p->d_lsmin,
+                       nullptr, p->lmax, p->d_mhi_full);
     DMWF_HIP(hipGetLastError());
     DMWF_HIP(hipStreamSynchronize(s));
     DMWF_HIP(hipFree(mant));
@@ -363,11 +431,20 @@ dmwf_status launch_seeds(dmwf_plan* p, hipStream_t s) {
     return DMWF_OK;
 }
 
+dmwf_status launch_mhi(dmwf_plan* p, const int* ell_dev, int* mhi, hipStream_t s) {
+    ProfScope ps(p, s, PROF_MISC);
+    hipLaunchKernelGGL(k_mhi, dim3((p->nq + 63) / 64), dim3(64), 0, s, p->lmax, p->nq, p->d_lsmin,
+                       ell_dev, 0, mhi);
+    DMWF_HIP(hipGetLastError());
+    return DMWF_OK;
+}
+
 dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const int* ell_dev,
                            hipStream_t s) {
-    SynArgs a{p->d_x, p->d_ls, p->d_s0, p->d_s1, p->d_A, ap, spec, ell_dev, p->lmax, p->nq};
+    SynArgs a{p->d_x, p->d_ls, p->d_s0, p->d_s1, p->d_A, ap, spec, ell_dev, p->lmax, p->nq, p->lp};
     ProfScope ps(p, s, PROF_LEG_SYN);
-    hipLaunchKernelGGL(k_leg_syn<kSynK>, dim3(p->nchunk_syn, p->lmax + 1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_leg_syn<kSynK>, dim3(p->nchunk_syn, (p->lmax + kLegWaves) / kLegWaves),
+                       dim3(64 * kLegWaves), 0, s, a);
     DMWF_HIP(hipGetLastError());
     return DMWF_OK;
 }
@@ -375,9 +452,10 @@ dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const
 dmwf_status launch_leg_ana(dmwf_plan* p, const double2* spec, double2* part, const int* ell_dev,
                            hipStream_t s) {
     AnaArgs a{p->d_x,  p->d_ls, p->d_s0, p->d_s1, p->d_A, spec, part,
-              (size_t)p->nalm + kTablePad, ell_dev, p->lmax, p->nq};
+              (size_t)p->nalm + kTablePad, ell_dev, p->lmax, p->nq, p->lp};
     ProfScope ps(p, s, PROF_LEG_ANA);
-    hipLaunchKernelGGL(k_leg_ana<kAnaK>, dim3(p->nchunk_ana, p->lmax + 1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_leg_ana<kAnaK>, dim3(p->nchunk_ana, (p->lmax + kLegWaves) / kLegWaves),
+                       dim3(64 * kLegWaves), 0, s, a);
     DMWF_HIP(hipGetLastError());
     return DMWF_OK;
 }

@@ -39,7 +39,7 @@ enum PixSource { PIX_MAP = 0, PIX_FIRST = 1, PIX_WRES = 2, PIX_WD = 3, PIX_CRES 
 
 struct RingArgs {
     RingGeom g;
-    int nq, lmax;
+    int nq, lmax, lp;
     const int* ell_syn;
     const int* ell_ana;
     double2* spec;
@@ -47,6 +47,8 @@ struct RingArgs {
     int pix;
     RingIO io;
     const int* qlist;
+    const int* mhi_syn;
+    const int* mhi_ana;
     const int* Mq;
     const int* blue;
     const long long* coff;
@@ -64,68 +66,163 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
 
-__device__ __forceinline__ int brev(int k, int logM) {
-    return logM ? (int)(__brev((unsigned)k) >> (32 - logM)) : 0;
-}
+// LDS layout: logical element e lives at e + e/16 (one pad slot per 16) so
+// that sixteen lanes touching sixteen consecutive butterflies' outputs of the
+// first pass fall in distinct banks.
+__device__ __forceinline__ int pad(int e) { return e + (e >> 4); }
 
-// R fused radix-2 DIT stages starting at sub-transform length 2^s.
-template <int R>
-__device__ __forceinline__ void fft_pass(double2* __restrict__ buf, int M, int s,
-                                         const double2* __restrict__ W, int wlog, int tid, int nt) {
-    constexpr int P = 1 << R;
-    const int L = 1 << s;
-    const int nb = M >> R;
-    for (int b = tid; b < nb; b += nt) {
-        const int j = b & (L - 1);
-        const int base = ((b >> s) << (s + R)) + j;
-        double2 v[P];
-#pragma unroll
-        for (int t = 0; t < P; ++t) v[t] = buf[base + t * L];
-#pragma unroll
-        for (int st = 0; st < R; ++st) {
-            const int half = 1 << st;
-#pragma unroll
-            for (int t = 0; t < P; ++t) {
-                if (t & half) continue;
-                const int jj = j + (t & (half - 1)) * L;
-                const double2 tw = W[jj << (wlog - s - st - 1)];
-                const double2 x2 = cmul(tw, v[t + half]);
-                v[t + half] = csub(v[t], x2);
-                v[t] = cadd(v[t], x2);
-            }
+constexpr int ilog2(int r) { return r <= 1 ? 0 : 1 + ilog2(r >> 1); }
+__device__ __forceinline__ int ilog2_rt(int v) { return 31 - __clz(v); }
+constexpr int bitrev(int i, int bits) { return bits == 0 ? 0 : ((i & 1) << (bits - 1)) | bitrev(i >> 1, bits - 1); }
+
+// cos and sin of k pi / 8, k = 0..7
+__device__ constexpr double kC8[8] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
+                                      0.38268343236508977173, 0.0, -0.38268343236508977173,
+                                      -0.70710678118654752440, -0.92387953251128675613};
+__device__ constexpr double kS8[8] = {0.0, 0.38268343236508977173, 0.70710678118654752440,
+                                      0.92387953251128675613, 1.0, 0.92387953251128675613,
+                                      0.70710678118654752440, 0.38268343236508977173};
+
+// Element i of the bit-reversal permutation of v (all indices compile-time).
+template <int R, int I>
+__device__ __forceinline__ void bitrev_swap(double2 (&v)[R]) {
+    if constexpr (I < R) {
+        constexpr int J = bitrev(I, ilog2(R));
+        if constexpr (I < J) {
+            const double2 t = v[I];
+            v[I] = v[J];
+            v[J] = t;
         }
+        bitrev_swap<R, I + 1>(v);
+    }
+}
+
+// One radix-2 DIT stage combining length-H sub-transforms, butterfly (B, K).
+template <int R, int H, int B, int K>
+__device__ __forceinline__ void dit_butterflies(double2 (&v)[R]) {
+    if constexpr (B < R) {
+        if constexpr (K < H) {
+            constexpr int idx = K * (8 / H);  // e^{-i pi K / H}
+            const double2 x1 = v[B + K];
+            double2 x2 = v[B + K + H];
+            if constexpr (K != 0) x2 = cmul(make_double2(kC8[idx], -kS8[idx]), x2);
+            v[B + K] = cadd(x1, x2);
+            v[B + K + H] = csub(x1, x2);
+            dit_butterflies<R, H, B, K + 1>(v);
+        } else {
+            dit_butterflies<R, H, B + 2 * H, 0>(v);
+        }
+    }
+}
+
+template <int R, int H>
+__device__ __forceinline__ void dit_stages(double2 (&v)[R]) {
+    if constexpr (H < R) {
+        dit_butterflies<R, H, 0, 0>(v);
+        dit_stages<R, 2 * H>(v);
+    }
+}
+
+// Radix-R DFT in registers, natural order in and out: V_t = sum_r v_r e^{-2 pi i r t / R}.
+template <int R>
+__device__ __forceinline__ void dft_small(double2 (&v)[R]) {
+    bitrev_swap<R, 0>(v);
+    dit_stages<R, 1>(v);
+}
+
+// One Stockham pass of radix R at stride Ns: butterfly j reads elements
+// j + r M/R, twiddles them by e^{-2 pi i (j mod Ns) r / (Ns R)}, transforms,
+// and writes (j / Ns) Ns R + (j mod Ns) + t Ns.  Each thread holds BPT
+// butterflies (j = tid + i nt) in registers between the read and the write,
+// which makes the pass safe in place; requires M / R <= BPT nt.
+template <int R, int BPT>
+__device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int M, int Ns,
+                                              const double2* __restrict__ W, int wlog, int tid,
+                                              int nt) {
+    const int nb = M / R;
+    const int stride = M / R;
+    double2 v[BPT][R];
+    const int sh = wlog - ilog2_rt(Ns * R);
 #pragma unroll
-        for (int t = 0; t < P; ++t) buf[base + t * L] = v[t];
+    for (int i = 0; i < BPT; ++i) {
+        const int j = tid + i * nt;
+        if (j < nb) {
+            const int k = j & (Ns - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = buf[pad(j + r * stride)];
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[i][r] = cmul(W[(k * r) << sh], v[i][r]);
+            }
+            dft_small<R>(v[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int j = tid + i * nt;
+        if (j < nb) {
+            const int k = j & (Ns - 1);
+            const int o = (j / Ns) * Ns * R + k;
+#pragma unroll
+            for (int t = 0; t < R; ++t) buf[pad(o + t * Ns)] = v[i][t];
+        }
+    }
+    __syncthreads();
+}
+
+// Forward DFT of length M = 2^logM in place, natural order in and out:
+// radix-16 passes while at least four bits remain, then one pass of radix
+// 2, 4 or 8 with up to 16 values per thread.
+__device__ __forceinline__ void fft(double2* buf, int M, int logM, const double2* W, int wlog,
+                                    int tid, int nt) {
+    int left = logM, Ns = 1;
+    while (left >= 4) {
+        stockham_pass<16, 1>(buf, M, Ns, W, wlog, tid, nt);
+        Ns <<= 4;
+        left -= 4;
+    }
+    if (left > 0) {
+        const int nb = M >> left;
+        const int bpt = nb > nt ? nb / nt : 1;
+        if (left == 3) {
+            if (bpt == 1) stockham_pass<8, 1>(buf, M, Ns, W, wlog, tid, nt);
+            else stockham_pass<8, 2>(buf, M, Ns, W, wlog, tid, nt);
+        } else if (left == 2) {
+            if (bpt == 1) stockham_pass<4, 1>(buf, M, Ns, W, wlog, tid, nt);
+            else if (bpt == 2) stockham_pass<4, 2>(buf, M, Ns, W, wlog, tid, nt);
+            else stockham_pass<4, 4>(buf, M, Ns, W, wlog, tid, nt);
+        } else {
+            if (bpt == 1) stockham_pass<2, 1>(buf, M, Ns, W, wlog, tid, nt);
+            else if (bpt == 2) stockham_pass<2, 2>(buf, M, Ns, W, wlog, tid, nt);
+            else if (bpt == 4) stockham_pass<2, 4>(buf, M, Ns, W, wlog, tid, nt);
+            else stockham_pass<2, 8>(buf, M, Ns, W, wlog, tid, nt);
+        }
     }
 }
 
-// Forward DFT in place: bit-reversed input, natural-order output.
-__device__ void fft(double2* buf, int M, int logM, const double2* W, int wlog, int tid, int nt) {
-    int s = 0;
-    while (s < logM) {
-        const int r = min(3, logM - s);
-        if (r == 3) fft_pass<3>(buf, M, s, W, wlog, tid, nt);
-        else if (r == 2) fft_pass<2>(buf, M, s, W, wlog, tid, nt);
-        else fft_pass<1>(buf, M, s, W, wlog, tid, nt);
-        __syncthreads();
-        s += r;
-    }
-}
-
-// buf holds a (bit-reversed, zero-padded).  Leaves buf_k = conj(conv_k) in
-// natural order, conv = a (*) b cyclic of length M, so the length-n forward
+// buf holds a (natural order, zero-padded to M).  Leaves buf_k = conj(conv_k),
+// conv = a (*) b the cyclic convolution of length M, so the length-n forward
 // DFT of the chirped input is X_k = conj(c_k buf_k).
-__device__ void bluestein(double2* buf, int M, int logM, const double2* __restrict__ B,
+__device__ __forceinline__ void bluestein(double2* buf, int M, int logM, const double2* __restrict__ B,
                           const double2* W, int wlog, int tid, int nt) {
     fft(buf, M, logM, W, wlog, tid, nt);
     const double inv = 1.0 / M;
-    for (int k = tid; k < M; k += nt) {
-        const int kr = brev(k, logM);
-        if (k <= kr) {
-            const double2 ak = cmul(buf[k], B[k]);
-            const double2 akr = cmul(buf[kr], B[kr]);
-            buf[kr] = make_double2(ak.x * inv, -ak.y * inv);
-            buf[k] = make_double2(akr.x * inv, -akr.y * inv);
+    // eight filter values in flight per thread before they are used
+    for (int k0 = tid; k0 < M; k0 += 8 * nt) {
+        double2 b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u * nt;
+            b[u] = k < M ? B[k] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u * nt;
+            if (k < M) {
+                const double2 ak = cmul(buf[pad(k)], b[u]);
+                buf[pad(k)] = make_double2(ak.x * inv, -ak.y * inv);
+            }
         }
     }
     __syncthreads();
@@ -162,80 +259,146 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     const double c = a.g.phi0pi[q];
     const bool eq = (q == a.nq - 1);
     const long long st0 = a.g.start_n[q], st1 = a.g.start_s[q];
-    const int ell = *a.ell_syn;
-    const int ella = *a.ell_ana;
+    const int ell = min(*a.ell_syn, a.mhi_syn[q]);
+    const int ella = min(*a.ell_ana, a.mhi_ana[q]);
     const int tid = threadIdx.x;
-    const size_t nq = a.nq;
     double rn[J], rs[J];
 
     const bool syn = (a.mode == RING_SYN || a.mode == RING_ITER || a.mode == RING_SYN_WRES);
     if (syn) {
-        // x_k = conj(Z_k) [times conj(c_k)], Z_k = H^N_k + i H^S_k, at bit-reversed slots
-        for (int k = tid; k < M; k += NT) {
-            double2 v = make_double2(0.0, 0.0);
-            if (k < n) {
-                double2 hn = make_double2(0.0, 0.0), hs = make_double2(0.0, 0.0);
-                for (int pass = 0; pass < 2; ++pass) {
-                    // pass 0: m = k + t n (m >= 0); pass 1: m = -k mod n + t n, conjugated (-m)
-                    int m = pass == 0 ? k : (k == 0 ? n : n - k);
-                    for (; m <= ell; m += n) {
-                        double sn, cs;
-                        sincospi(m * c, &sn, &cs);
-                        const double2 ph = make_double2(cs, sn);
-                        double2 fn = a.spec[((size_t)m * nq + q) * 2 + 0];
-                        double2 fs = a.spec[((size_t)m * nq + q) * 2 + 1];
-                        if (m == 0) {
-                            fn.y = 0.0;
-                            fs.y = 0.0;
-                        }
-                        double2 en = cmul(fn, ph), es = cmul(fs, ph);
-                        if (pass == 1) {
-                            en = conj2(en);
-                            es = conj2(es);
-                        }
-                        hn = cadd(hn, en);
-                        hs = cadd(hs, es);
+        // Fold F into the DFT input x_k = conj(Z_k) [times conj(c_k)],
+        // Z_k = H^N_k + i H^S_k, H_k = sum over m = k mod n of F_m e^{i m phi0}
+        // with F_{-m} = conj(F_m).  The row of F is read once, coalesced, and
+        // scattered: m feeds bin m mod n, and -m feeds bin -m mod n.
+        const double2* Fq = a.spec + (size_t)q * a.lp * 2;
+        const bool alias = 2 * ell >= n;
+        if (alias) {
+            for (int k = tid; k < M; k += NT) buf[pad(k)] = make_double2(0.0, 0.0);
+            __syncthreads();
+        } else {
+            for (int k = tid; k < M; k += NT)
+                if (k >= n || (k > ell && k < n - ell)) buf[pad(k)] = make_double2(0.0, 0.0);
+        }
+        for (int m0 = tid; m0 <= ell; m0 += 4 * NT) {
+            // loads for four m first (F row entries and the chirp at their bins)
+            double2 fnv[4], fsv[4], cpv[4], cmv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int m = m0 + u * NT;
+                fnv[u] = fsv[u] = cpv[u] = cmv[u] = make_double2(0.0, 0.0);
+                if (m <= ell) {
+                    fnv[u] = Fq[2 * m];
+                    fsv[u] = Fq[2 * m + 1];
+                    if (blue && !alias) {
+                        const int kp = m % n;
+                        cpv[u] = ch[kp];
+                        cmv[u] = ch[kp == 0 ? 0 : n - kp];
                     }
                 }
-                if (eq) hs = make_double2(0.0, 0.0);
-                // conj(Z) = conj(hn + i hs)
-                v = make_double2(hn.x - hs.y, -(hn.y + hs.x));
-                if (blue) v = cmul(v, conj2(ch[k]));
             }
-            buf[brev(k, logM)] = v;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int m = m0 + u * NT;
+                if (m > ell) continue;
+                double sn, cs;
+                sincospi(m * c, &sn, &cs);
+                const double2 ph = make_double2(cs, sn);
+                double2 fn = fnv[u], fs = fsv[u];
+                if (m == 0) {
+                    fn.y = 0.0;
+                    fs.y = 0.0;
+                }
+                if (eq) fs = make_double2(0.0, 0.0);
+                const double2 en = cmul(fn, ph), es = cmul(fs, ph);
+                // contribution of +m: en + i es; of -m: conj(en) + i conj(es)
+                const double2 zp = make_double2(en.x - es.y, en.y + es.x);
+                const double2 zm = make_double2(en.x + es.y, es.x - en.y);
+                const int kp = m % n;
+                const int km = kp == 0 ? 0 : n - kp;
+                if (alias) {
+                    atomicAdd(&buf[pad(kp)].x, zp.x);
+                    atomicAdd(&buf[pad(kp)].y, zp.y);
+                    if (m > 0) {
+                        atomicAdd(&buf[pad(km)].x, zm.x);
+                        atomicAdd(&buf[pad(km)].y, zm.y);
+                    }
+                } else {
+                    double2 v = conj2(zp);
+                    if (blue) v = cmul(v, conj2(cpv[u]));
+                    buf[pad(kp)] = v;
+                    if (m > 0) {
+                        double2 w2 = conj2(zm);
+                        if (blue) w2 = cmul(w2, conj2(cmv[u]));
+                        buf[pad(km)] = w2;
+                    }
+                }
+            }
         }
         __syncthreads();
+        if (alias) {
+            for (int k = tid; k < n; k += NT) {
+                double2 v = conj2(buf[pad(k)]);
+                if (blue) v = cmul(v, conj2(ch[k]));
+                buf[pad(k)] = v;
+            }
+            __syncthreads();
+        }
         if (blue) bluestein(buf, M, logM, B, a.W, a.wlog, tid, NT);
         else fft(buf, M, logM, a.W, a.wlog, tid, NT);
         // y_j = IDFT(Z)_j: blue: c_j buf_j; else conj(buf_j).  s^N = Re y, s^S = Im y.
+        // Pixel data are loaded for all of the thread's pixels first, then
+        // combined and stored, so the loads of one pixel never wait on the
+        // store of another.
         double num = 0.0, den = 0.0;
+        double yN[J], yS[J], dN[J], dS[J], wN[J], wS[J], pN[J], pS[J];
+#pragma unroll
+        for (int t = 0; t < J; ++t) {
+            const int j = tid + t * NT;
+            yN[t] = yS[t] = dN[t] = dS[t] = wN[t] = wS[t] = pN[t] = pS[t] = 0.0;
+            if (j < n) {
+                const double2 y = blue ? cmul(ch[j], buf[pad(j)]) : conj2(buf[pad(j)]);
+                yN[t] = y.x;
+                yS[t] = y.y;
+                if (a.mode != RING_SYN) {
+                    dN[t] = a.io.d[st0 + j];
+                    wN[t] = a.io.w[st0 + j];
+                    if (!eq) {
+                        dS[t] = a.io.d[st1 + j];
+                        wS[t] = a.io.w[st1 + j];
+                    }
+                    if (a.mode == RING_ITER && !a.io.first) {
+                        pN[t] = a.io.s_map[st0 + j];
+                        if (!eq) pS[t] = a.io.s_map[st1 + j];
+                    }
+                }
+            }
+        }
 #pragma unroll
         for (int t = 0; t < J; ++t) {
             const int j = tid + t * NT;
             rn[t] = 0.0;
             rs[t] = 0.0;
             if (j >= n) continue;
-            const double2 y = blue ? cmul(ch[j], buf[j]) : conj2(buf[j]);
-            for (int h = 0; h < (eq ? 1 : 2); ++h) {
-                const double s = h == 0 ? y.x : y.y;
-                const long long p = (h == 0 ? st0 : st1) + j;
-                double r = 0.0;
-                if (a.mode == RING_SYN) {
-                    a.io.map_out[p] = s;
-                } else if (a.mode == RING_SYN_WRES) {
-                    r = a.io.w[p] * (a.io.d[p] - s);
-                } else {
-                    const double sp = a.io.first ? 0.0 : a.io.s_map[p];
-                    const double ds = s - sp;
+            if (a.mode == RING_SYN) {
+                a.io.map_out[st0 + j] = yN[t];
+                if (!eq) a.io.map_out[st1 + j] = yS[t];
+            } else if (a.mode == RING_SYN_WRES) {
+                rn[t] = wN[t] * (dN[t] - yN[t]);
+                rs[t] = eq ? 0.0 : wS[t] * (dS[t] - yS[t]);
+            } else {
+                const double xi = a.io.xi, xa = a.io.xi - a.io.alpha;
+                double ds = yN[t] - pN[t];
+                num = fma(ds, ds, num);
+                den = fma(yN[t], yN[t], den);
+                a.io.s_map[st0 + j] = yN[t];
+                rn[t] = xi * wN[t] / fma(xa, wN[t], 1.0) * (dN[t] - yN[t]);
+                if (!eq) {
+                    ds = yS[t] - pS[t];
                     num = fma(ds, ds, num);
-                    den = fma(s, s, den);
-                    a.io.s_map[p] = s;
-                    const double w = a.io.w[p];
-                    const double cc = a.io.xi * w / fma(a.io.xi - a.io.alpha, w, 1.0);
-                    r = cc * (a.io.d[p] - s);
+                    den = fma(yS[t], yS[t], den);
+                    a.io.s_map[st1 + j] = yS[t];
+                    rs[t] = xi * wS[t] / fma(xa, wS[t], 1.0) * (dS[t] - yS[t]);
                 }
-                if (h == 0) rn[t] = r;
-                else rs[t] = r;
             }
         }
         if (a.mode == RING_ITER) {
@@ -282,36 +445,53 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
         if (j < n) {
             double2 z = make_double2(rn[t], rs[t]);
             if (blue) z = cmul(z, conj2(ch[j]));
-            buf[brev(j, logM)] = z;
+            buf[pad(j)] = z;
         }
     }
-    for (int j = n + tid; j < M; j += NT) buf[brev(j, logM)] = make_double2(0.0, 0.0);
+    for (int j = n + tid; j < M; j += NT) buf[pad(j)] = make_double2(0.0, 0.0);
     __syncthreads();
     if (blue) bluestein(buf, M, logM, B, a.W, a.wlog, tid, NT);
     else fft(buf, M, logM, a.W, a.wlog, tid, NT);
     // Z_k = DFT(z)_k; split the two real rings and unfold to m
-    for (int m = tid; m <= ella; m += NT) {
-        const int k = m % n;
-        const int kc = k == 0 ? 0 : n - k;
-        double2 zk = buf[k], zc = buf[kc];
-        if (blue) {
-            zk = conj2(cmul(ch[k], zk));
-            zc = conj2(cmul(ch[kc], zc));
+    for (int m0 = tid; m0 <= ella; m0 += 4 * NT) {
+        double2 ckv[4], ccv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int m = m0 + u * NT;
+            ckv[u] = ccv[u] = make_double2(1.0, 0.0);
+            if (blue && m <= ella) {
+                const int k = m % n;
+                ckv[u] = ch[k];
+                ccv[u] = ch[k == 0 ? 0 : n - k];
+            }
         }
-        const double2 czc = conj2(zc);
-        const double2 rN = make_double2(0.5 * (zk.x + czc.x), 0.5 * (zk.y + czc.y));
-        const double2 dS = csub(zk, czc);  // R^S = -i dS / 2
-        const double2 rS = make_double2(0.5 * dS.y, -0.5 * dS.x);
-        double sn, cs;
-        sincospi(m * c, &sn, &cs);
-        const double2 ph = make_double2(cs, -sn);
-        double2 gN = cmul(rN, ph), gS = eq ? make_double2(0.0, 0.0) : cmul(rS, ph);
-        if (m == 0) {
-            gN.y = 0.0;
-            gS.y = 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int m = m0 + u * NT;
+            if (m > ella) continue;
+            const int k = m % n;
+            const int kc = k == 0 ? 0 : n - k;
+            double2 zk = buf[pad(k)], zc = buf[pad(kc)];
+            if (blue) {
+                zk = conj2(cmul(ckv[u], zk));
+                zc = conj2(cmul(ccv[u], zc));
+            }
+            const double2 czc = conj2(zc);
+            const double2 rN = make_double2(0.5 * (zk.x + czc.x), 0.5 * (zk.y + czc.y));
+            const double2 dS = csub(zk, czc);  // R^S = -i dS / 2
+            const double2 rS = make_double2(0.5 * dS.y, -0.5 * dS.x);
+            double sn, cs;
+            sincospi(m * c, &sn, &cs);
+            const double2 ph = make_double2(cs, -sn);
+            double2 gN = cmul(rN, ph), gS = eq ? make_double2(0.0, 0.0) : cmul(rS, ph);
+            if (m == 0) {
+                gN.y = 0.0;
+                gS.y = 0.0;
+            }
+            double2* g = a.spec + ((size_t)q * a.lp + m) * 2;
+            g[0] = gN;
+            g[1] = gS;
         }
-        a.spec[((size_t)m * nq + q) * 2 + 0] = gN;
-        a.spec[((size_t)m * nq + q) * 2 + 1] = gS;
     }
 }
 
@@ -335,18 +515,19 @@ __global__ __launch_bounds__(NT) void k_chirp_spectrum(const int* __restrict__ q
         double2 v = make_double2(0.0, 0.0);
         if (t < n) v = ch[t];
         else if (M - t < n) v = ch[M - t];
-        buf[brev(t, logM)] = v;
+        buf[pad(t)] = v;
     }
     __syncthreads();
     fft(buf, M, logM, W, wlog, threadIdx.x, NT);
-    for (int k = threadIdx.x; k < M; k += NT) bspec[boff[q] + k] = buf[k];
+    for (int k = threadIdx.x; k < M; k += NT) bspec[boff[q] + k] = buf[pad(k)];
 }
 
 int ring_class(int M) { return M <= 1024 ? 0 : (M == 2048 ? 1 : (M == 4096 ? 2 : 3)); }
 
+// Threads per class: the FFT keeps at most 16 elements per thread.
 void launch_class(int cls, dim3 grid, size_t lds, hipStream_t s, const RingArgs& a) {
     switch (cls) {
-        case 0: hipLaunchKernelGGL((k_ring_fft<256, 4>), grid, dim3(256), lds, s, a); break;
+        case 0: hipLaunchKernelGGL((k_ring_fft<128, 8>), grid, dim3(128), lds, s, a); break;
         case 1: hipLaunchKernelGGL((k_ring_fft<256, 8>), grid, dim3(256), lds, s, a); break;
         case 2: hipLaunchKernelGGL((k_ring_fft<512, 8>), grid, dim3(512), lds, s, a); break;
         default: hipLaunchKernelGGL((k_ring_fft<512, 8>), grid, dim3(512), lds, s, a); break;
@@ -354,6 +535,8 @@ void launch_class(int cls, dim3 grid, size_t lds, hipStream_t s, const RingArgs&
 }
 
 const int kClassMaxM[kRingClasses] = {1024, 2048, 4096, 8192};
+
+size_t class_lds(int c) { return (size_t)(kClassMaxM[c] + kClassMaxM[c] / 16) * sizeof(double2); }
 
 }  // namespace
 
@@ -395,12 +578,12 @@ dmwf_status build_ring_tables(dmwf_plan* p) {
         }
         Mmax = std::max(Mmax, M);
     }
-    // twiddles e^{-2 pi i t / Mmax}
+    // twiddles e^{-2 pi i t / Mmax}, full circle
     int wlog = 0;
     while ((1 << wlog) < Mmax) ++wlog;
-    std::vector<double2> W(Mmax / 2);
+    std::vector<double2> W(Mmax);
     const long double pi = 3.141592653589793238462643383279502884L;
-    for (int t = 0; t < Mmax / 2; ++t) {
+    for (int t = 0; t < Mmax; ++t) {
         const long double ang = -2.0L * pi * t / Mmax;
         W[t] = make_double2((double)cosl(ang), (double)sinl(ang));
     }
@@ -457,8 +640,8 @@ dmwf_status build_ring_tables(dmwf_plan* p) {
             set_error("allocation of ring list failed");
             return DMWF_ERR_OOM;
         }
-        const size_t lds = (size_t)kClassMaxM[c] * sizeof(double2);
-        hipLaunchKernelGGL((k_chirp_spectrum<256>), dim3(bl[c].size()), dim3(256), lds, nullptr, dq,
+        const size_t lds = class_lds(c);
+        hipLaunchKernelGGL((k_chirp_spectrum<512>), dim3(bl[c].size()), dim3(512), lds, nullptr, dq,
                            p->d_nph, p->d_ring_M, p->d_ring_coff, p->d_ring_boff, p->d_chirp,
                            p->d_bspec, p->d_twiddle, wlog);
         DMWF_HIP(hipGetLastError());
@@ -469,13 +652,17 @@ dmwf_status build_ring_tables(dmwf_plan* p) {
 }
 
 dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const int* ell_syn,
-                        const int* ell_ana, const RingIO& io, hipStream_t s) {
+                        const int* ell_ana, const int* mhi_syn, const int* mhi_ana,
+                        const RingIO& io, hipStream_t s) {
     RingArgs a;
     a.g = p->geom();
     a.nq = p->nq;
     a.lmax = p->lmax;
+    a.lp = p->lp;
     a.ell_syn = ell_syn;
     a.ell_ana = ell_ana;
+    a.mhi_syn = mhi_syn;
+    a.mhi_ana = mhi_ana;
     a.spec = spec;
     a.io = io;
     a.Mq = p->d_ring_M;
@@ -505,7 +692,7 @@ dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const int* e
         if (nb == 0) continue;
         a.qlist = p->d_ring_class + p->class_off[c];
         ProfScope ps(p, s, cls);
-        launch_class(c, dim3(nb), (size_t)kClassMaxM[c] * sizeof(double2), s, a);
+        launch_class(c, dim3(nb), class_lds(c), s, a);
         DMWF_HIP(hipGetLastError());
     }
     return DMWF_OK;
