@@ -106,8 +106,6 @@ struct dmwf_plan {
     int* d_ring_blue = nullptr;        // per q: 1 if the ring length is not a power of two
     long long* d_ring_coff = nullptr;  // per q: offset into the chirp table
     long long* d_ring_boff = nullptr;  // per q: offset into the filter-spectrum table
-    double2* d_twiddle = nullptr;      // e^{-2 pi i t / Mmax}, t < Mmax / 2
-    int twiddle_log = 0;               // log2 Mmax
     double2* d_chirp = nullptr;        // e^{i pi t^2 / n}, t < n, per Bluestein ring
     double2* d_bspec = nullptr;        // FFT_M of the chirp filter, per Bluestein ring
     int* d_ring_class = nullptr;       // q lists of the launch classes, concatenated

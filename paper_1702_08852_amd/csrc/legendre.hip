@@ -378,7 +378,9 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
     const double* A = a.A + base;
     const int L0 = m + ((lo - m) & ~1);
     for (int l = m + lane; l < L0; l += 64) out[l] = make_double2(0.0, 0.0);
-    const int rb = lane >> 2, rp = lane & 3;
+    // lane reads row rb = lane & 15 (sixteen rows in distinct banks per
+    // 16-lane group), part rp = lane >> 4; parts combine across lanes 16 apart
+    const int rb = lane & 15, rp = lane >> 4;
     for (int l0 = L0; l0 <= ell; l0 += kAnaB) {
         double accr[kAnaB], acci[kAnaB];
         if (l0 <= hi)
@@ -395,10 +397,10 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
             sr += v.x;
             si += v.y;
         }
-        sr += __shfl_xor(sr, 1);
-        si += __shfl_xor(si, 1);
-        sr += __shfl_xor(sr, 2);
-        si += __shfl_xor(si, 2);
+        sr += __shfl_xor(sr, 16);
+        si += __shfl_xor(si, 16);
+        sr += __shfl_xor(sr, 32);
+        si += __shfl_xor(si, 32);
         wave_lds_sync();
         if (rp == 0 && l0 + rb <= ell) out[l0 + rb] = make_double2(sr, si);
     }

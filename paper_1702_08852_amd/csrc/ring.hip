@@ -53,8 +53,6 @@ struct RingArgs {
     const int* blue;
     const long long* coff;
     const long long* boff;
-    const double2* W;
-    int wlog;
     const double2* chirp;
     const double2* bspec;
 };
@@ -136,13 +134,11 @@ __device__ __forceinline__ void dft_small(double2 (&v)[R]) {
 // butterflies (j = tid + i nt) in registers between the read and the write,
 // which makes the pass safe in place; requires M / R <= BPT nt.
 template <int R, int BPT>
-__device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int M, int Ns,
-                                              const double2* __restrict__ W, int wlog, int tid,
+__device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int M, int Ns, int tid,
                                               int nt) {
     const int nb = M / R;
     const int stride = M / R;
     double2 v[BPT][R];
-    const int sh = wlog - ilog2_rt(Ns * R);
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
         const int j = tid + i * nt;
@@ -151,8 +147,23 @@ __device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int M, 
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i][r] = buf[pad(j + r * stride)];
             if (Ns > 1) {
+                // w^r, w = e^{-2 pi i k / (Ns R)}: one sincospi and a product
+                // tree of depth at most four (a few ulps), no table loads
+                double sn, cs;
+                sincospi(-2.0 * k / (Ns * R), &sn, &cs);
+                double2 wp[4];  // w^1, w^2, w^4, w^8
+                wp[0] = make_double2(cs, sn);
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[i][r] = cmul(W[(k * r) << sh], v[i][r]);
+                for (int b = 1; b < 4; ++b) wp[b] = cmul(wp[b - 1], wp[b - 1]);
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    // w^r from the binary digits of r, used at once
+                    double2 t = wp[ilog2(r & -r)];
+#pragma unroll
+                    for (int b = ilog2(r & -r) + 1; b < 4; ++b)
+                        if (r & (1 << b)) t = cmul(t, wp[b]);
+                    v[i][r] = cmul(t, v[i][r]);
+                }
             }
             dft_small<R>(v[i]);
         }
@@ -172,31 +183,34 @@ __device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int M, 
 }
 
 // Forward DFT of length M = 2^logM in place, natural order in and out:
-// radix-16 passes while at least four bits remain, then one pass of radix
-// 2, 4 or 8 with up to 16 values per thread.
-__device__ __forceinline__ void fft(double2* buf, int M, int logM, const double2* W, int wlog,
-                                    int tid, int nt) {
+// radix-RMAX passes while enough bits remain, then one pass of a smaller
+// radix with up to 16 values per thread.
+template <int RMAX>
+__device__ __forceinline__ void fft(double2* buf, int M, int logM, int tid, int nt) {
+    constexpr int LR = ilog2(RMAX);
     int left = logM, Ns = 1;
-    while (left >= 4) {
-        stockham_pass<16, 1>(buf, M, Ns, W, wlog, tid, nt);
-        Ns <<= 4;
-        left -= 4;
+    while (left >= LR) {
+        const int nb = M >> LR;
+        if (nb > nt) stockham_pass<RMAX, (RMAX == 16 ? 1 : 2)>(buf, M, Ns, tid, nt);
+        else stockham_pass<RMAX, 1>(buf, M, Ns, tid, nt);
+        Ns <<= LR;
+        left -= LR;
     }
     if (left > 0) {
         const int nb = M >> left;
         const int bpt = nb > nt ? nb / nt : 1;
         if (left == 3) {
-            if (bpt == 1) stockham_pass<8, 1>(buf, M, Ns, W, wlog, tid, nt);
-            else stockham_pass<8, 2>(buf, M, Ns, W, wlog, tid, nt);
+            if (bpt == 1) stockham_pass<8, 1>(buf, M, Ns, tid, nt);
+            else stockham_pass<8, 2>(buf, M, Ns, tid, nt);
         } else if (left == 2) {
-            if (bpt == 1) stockham_pass<4, 1>(buf, M, Ns, W, wlog, tid, nt);
-            else if (bpt == 2) stockham_pass<4, 2>(buf, M, Ns, W, wlog, tid, nt);
-            else stockham_pass<4, 4>(buf, M, Ns, W, wlog, tid, nt);
+            if (bpt == 1) stockham_pass<4, 1>(buf, M, Ns, tid, nt);
+            else if (bpt == 2) stockham_pass<4, 2>(buf, M, Ns, tid, nt);
+            else stockham_pass<4, 4>(buf, M, Ns, tid, nt);
         } else {
-            if (bpt == 1) stockham_pass<2, 1>(buf, M, Ns, W, wlog, tid, nt);
-            else if (bpt == 2) stockham_pass<2, 2>(buf, M, Ns, W, wlog, tid, nt);
-            else if (bpt == 4) stockham_pass<2, 4>(buf, M, Ns, W, wlog, tid, nt);
-            else stockham_pass<2, 8>(buf, M, Ns, W, wlog, tid, nt);
+            if (bpt == 1) stockham_pass<2, 1>(buf, M, Ns, tid, nt);
+            else if (bpt == 2) stockham_pass<2, 2>(buf, M, Ns, tid, nt);
+            else if (bpt == 4) stockham_pass<2, 4>(buf, M, Ns, tid, nt);
+            else stockham_pass<2, 8>(buf, M, Ns, tid, nt);
         }
     }
 }
@@ -204,9 +218,10 @@ __device__ __forceinline__ void fft(double2* buf, int M, int logM, const double2
 // buf holds a (natural order, zero-padded to M).  Leaves buf_k = conj(conv_k),
 // conv = a (*) b the cyclic convolution of length M, so the length-n forward
 // DFT of the chirped input is X_k = conj(c_k buf_k).
+template <int RMAX>
 __device__ __forceinline__ void bluestein(double2* buf, int M, int logM, const double2* __restrict__ B,
-                          const double2* W, int wlog, int tid, int nt) {
-    fft(buf, M, logM, W, wlog, tid, nt);
+                                          int tid, int nt) {
+    fft<RMAX>(buf, M, logM, tid, nt);
     const double inv = 1.0 / M;
     // eight filter values in flight per thread before they are used
     for (int k0 = tid; k0 < M; k0 += 8 * nt) {
@@ -226,7 +241,7 @@ __device__ __forceinline__ void bluestein(double2* buf, int M, int logM, const d
         }
     }
     __syncthreads();
-    fft(buf, M, logM, W, wlog, tid, nt);
+    fft<RMAX>(buf, M, logM, tid, nt);
 }
 
 template <int NT>
@@ -245,7 +260,7 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
     return t;
 }
 
-template <int NT, int J>
+template <int NT, int J, int RMAX>
 __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     extern __shared__ double2 buf[];
     __shared__ double red[NT / 64];
@@ -343,61 +358,66 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
             }
             __syncthreads();
         }
-        if (blue) bluestein(buf, M, logM, B, a.W, a.wlog, tid, NT);
-        else fft(buf, M, logM, a.W, a.wlog, tid, NT);
+        if (blue) bluestein<RMAX>(buf, M, logM, B, tid, NT);
+        else fft<RMAX>(buf, M, logM, tid, NT);
         // y_j = IDFT(Z)_j: blue: c_j buf_j; else conj(buf_j).  s^N = Re y, s^S = Im y.
         // Pixel data are loaded for all of the thread's pixels first, then
         // combined and stored, so the loads of one pixel never wait on the
         // store of another.
         double num = 0.0, den = 0.0;
-        double yN[J], yS[J], dN[J], dS[J], wN[J], wS[J], pN[J], pS[J];
+        constexpr int JH = J > 4 ? 4 : J;  // pixels per half, bounds register use
 #pragma unroll
-        for (int t = 0; t < J; ++t) {
-            const int j = tid + t * NT;
-            yN[t] = yS[t] = dN[t] = dS[t] = wN[t] = wS[t] = pN[t] = pS[t] = 0.0;
-            if (j < n) {
-                const double2 y = blue ? cmul(ch[j], buf[pad(j)]) : conj2(buf[pad(j)]);
-                yN[t] = y.x;
-                yS[t] = y.y;
-                if (a.mode != RING_SYN) {
-                    dN[t] = a.io.d[st0 + j];
-                    wN[t] = a.io.w[st0 + j];
-                    if (!eq) {
-                        dS[t] = a.io.d[st1 + j];
-                        wS[t] = a.io.w[st1 + j];
-                    }
-                    if (a.mode == RING_ITER && !a.io.first) {
-                        pN[t] = a.io.s_map[st0 + j];
-                        if (!eq) pS[t] = a.io.s_map[st1 + j];
+        for (int t0 = 0; t0 < J; t0 += JH) {
+            double yN[JH], yS[JH], dN[JH], dS[JH], wN[JH], wS[JH], pN[JH], pS[JH];
+#pragma unroll
+            for (int u = 0; u < JH; ++u) {
+                const int j = tid + (t0 + u) * NT;
+                yN[u] = yS[u] = dN[u] = dS[u] = wN[u] = wS[u] = pN[u] = pS[u] = 0.0;
+                if (j < n) {
+                    const double2 y = blue ? cmul(ch[j], buf[pad(j)]) : conj2(buf[pad(j)]);
+                    yN[u] = y.x;
+                    yS[u] = y.y;
+                    if (a.mode != RING_SYN) {
+                        dN[u] = a.io.d[st0 + j];
+                        wN[u] = a.io.w[st0 + j];
+                        if (!eq) {
+                            dS[u] = a.io.d[st1 + j];
+                            wS[u] = a.io.w[st1 + j];
+                        }
+                        if (a.mode == RING_ITER && !a.io.first) {
+                            pN[u] = a.io.s_map[st0 + j];
+                            if (!eq) pS[u] = a.io.s_map[st1 + j];
+                        }
                     }
                 }
             }
-        }
 #pragma unroll
-        for (int t = 0; t < J; ++t) {
-            const int j = tid + t * NT;
-            rn[t] = 0.0;
-            rs[t] = 0.0;
-            if (j >= n) continue;
-            if (a.mode == RING_SYN) {
-                a.io.map_out[st0 + j] = yN[t];
-                if (!eq) a.io.map_out[st1 + j] = yS[t];
-            } else if (a.mode == RING_SYN_WRES) {
-                rn[t] = wN[t] * (dN[t] - yN[t]);
-                rs[t] = eq ? 0.0 : wS[t] * (dS[t] - yS[t]);
-            } else {
-                const double xi = a.io.xi, xa = a.io.xi - a.io.alpha;
-                double ds = yN[t] - pN[t];
-                num = fma(ds, ds, num);
-                den = fma(yN[t], yN[t], den);
-                a.io.s_map[st0 + j] = yN[t];
-                rn[t] = xi * wN[t] / fma(xa, wN[t], 1.0) * (dN[t] - yN[t]);
-                if (!eq) {
-                    ds = yS[t] - pS[t];
+            for (int u = 0; u < JH; ++u) {
+                const int t = t0 + u;
+                const int j = tid + t * NT;
+                rn[t] = 0.0;
+                rs[t] = 0.0;
+                if (j >= n) continue;
+                if (a.mode == RING_SYN) {
+                    a.io.map_out[st0 + j] = yN[u];
+                    if (!eq) a.io.map_out[st1 + j] = yS[u];
+                } else if (a.mode == RING_SYN_WRES) {
+                    rn[t] = wN[u] * (dN[u] - yN[u]);
+                    rs[t] = eq ? 0.0 : wS[u] * (dS[u] - yS[u]);
+                } else {
+                    const double xi = a.io.xi, xa = a.io.xi - a.io.alpha;
+                    double ds = yN[u] - pN[u];
                     num = fma(ds, ds, num);
-                    den = fma(yS[t], yS[t], den);
-                    a.io.s_map[st1 + j] = yS[t];
-                    rs[t] = xi * wS[t] / fma(xa, wS[t], 1.0) * (dS[t] - yS[t]);
+                    den = fma(yN[u], yN[u], den);
+                    a.io.s_map[st0 + j] = yN[u];
+                    rn[t] = xi * wN[u] / fma(xa, wN[u], 1.0) * (dN[u] - yN[u]);
+                    if (!eq) {
+                        ds = yS[u] - pS[u];
+                        num = fma(ds, ds, num);
+                        den = fma(yS[u], yS[u], den);
+                        a.io.s_map[st1 + j] = yS[u];
+                        rs[t] = xi * wS[u] / fma(xa, wS[u], 1.0) * (dS[u] - yS[u]);
+                    }
                 }
             }
         }
@@ -450,8 +470,8 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     }
     for (int j = n + tid; j < M; j += NT) buf[pad(j)] = make_double2(0.0, 0.0);
     __syncthreads();
-    if (blue) bluestein(buf, M, logM, B, a.W, a.wlog, tid, NT);
-    else fft(buf, M, logM, a.W, a.wlog, tid, NT);
+    if (blue) bluestein<RMAX>(buf, M, logM, B, tid, NT);
+    else fft<RMAX>(buf, M, logM, tid, NT);
     // Z_k = DFT(z)_k; split the two real rings and unfold to m
     for (int m0 = tid; m0 <= ella; m0 += 4 * NT) {
         double2 ckv[4], ccv[4];
@@ -504,8 +524,7 @@ __global__ __launch_bounds__(NT) void k_chirp_spectrum(const int* __restrict__ q
                                                        const long long* __restrict__ coff,
                                                        const long long* __restrict__ boff,
                                                        const double2* __restrict__ chirp,
-                                                       double2* __restrict__ bspec,
-                                                       const double2* __restrict__ W, int wlog) {
+                                                       double2* __restrict__ bspec) {
     extern __shared__ double2 buf[];
     const int q = qlist[blockIdx.x];
     const int n = nph[q], M = Mq[q];
@@ -518,19 +537,27 @@ __global__ __launch_bounds__(NT) void k_chirp_spectrum(const int* __restrict__ q
         buf[pad(t)] = v;
     }
     __syncthreads();
-    fft(buf, M, logM, W, wlog, threadIdx.x, NT);
+    fft<16>(buf, M, logM, threadIdx.x, NT);
     for (int k = threadIdx.x; k < M; k += NT) bspec[boff[q] + k] = buf[pad(k)];
 }
 
 int ring_class(int M) { return M <= 1024 ? 0 : (M == 2048 ? 1 : (M == 4096 ? 2 : 3)); }
 
 // Threads per class: the FFT keeps at most 16 elements per thread.
+#ifndef DMWF_RING_RMAX
+#define DMWF_RING_RMAX 16
+#endif
+#ifndef DMWF_RING_NT3
+#define DMWF_RING_NT3 512
+#endif
 void launch_class(int cls, dim3 grid, size_t lds, hipStream_t s, const RingArgs& a) {
+    constexpr int R = DMWF_RING_RMAX;
+    constexpr int NT3 = DMWF_RING_NT3;
     switch (cls) {
-        case 0: hipLaunchKernelGGL((k_ring_fft<128, 8>), grid, dim3(128), lds, s, a); break;
-        case 1: hipLaunchKernelGGL((k_ring_fft<256, 8>), grid, dim3(256), lds, s, a); break;
-        case 2: hipLaunchKernelGGL((k_ring_fft<512, 8>), grid, dim3(512), lds, s, a); break;
-        default: hipLaunchKernelGGL((k_ring_fft<512, 8>), grid, dim3(512), lds, s, a); break;
+        case 0: hipLaunchKernelGGL((k_ring_fft<128, 8, R>), grid, dim3(128), lds, s, a); break;
+        case 1: hipLaunchKernelGGL((k_ring_fft<256, 8, R>), grid, dim3(256), lds, s, a); break;
+        case 2: hipLaunchKernelGGL((k_ring_fft<512, 8, R>), grid, dim3(512), lds, s, a); break;
+        default: hipLaunchKernelGGL((k_ring_fft<NT3, 4096 / NT3, R>), grid, dim3(NT3), lds, s, a); break;
     }
 }
 
@@ -541,8 +568,8 @@ size_t class_lds(int c) { return (size_t)(kClassMaxM[c] + kClassMaxM[c] / 16) * 
 }  // namespace
 
 void free_ring_tables(dmwf_plan* p) {
-    void* bufs[] = {p->d_ring_M, p->d_ring_blue, p->d_ring_coff, p->d_ring_boff, p->d_twiddle,
-                    p->d_chirp,  p->d_bspec,     p->d_ring_class};
+    void* bufs[] = {p->d_ring_M, p->d_ring_blue, p->d_ring_coff, p->d_ring_boff, p->d_chirp,
+                    p->d_bspec,  p->d_ring_class};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -553,7 +580,6 @@ dmwf_status build_ring_tables(dmwf_plan* p) {
     std::vector<long long> coff(nq, 0), boff(nq, 0);
     const int N = p->nside;
     long long csum = 0, bsum = 0;
-    int Mmax = 4;
     for (int q = 0; q < nq; ++q) {
         const int r = q + 1;
         const int n = r < N ? 4 * r : 4 * N;
@@ -576,17 +602,8 @@ dmwf_status build_ring_tables(dmwf_plan* p) {
             csum += n;
             bsum += M;
         }
-        Mmax = std::max(Mmax, M);
     }
-    // twiddles e^{-2 pi i t / Mmax}, full circle
-    int wlog = 0;
-    while ((1 << wlog) < Mmax) ++wlog;
-    std::vector<double2> W(Mmax);
     const long double pi = 3.141592653589793238462643383279502884L;
-    for (int t = 0; t < Mmax; ++t) {
-        const long double ang = -2.0L * pi * t / Mmax;
-        W[t] = make_double2((double)cosl(ang), (double)sinl(ang));
-    }
     // chirps e^{i pi t^2 / n} with t^2 reduced mod 2n exactly
     std::vector<double2> C(std::max<long long>(csum, 1));
     for (int q = 0; q < nq; ++q) {
@@ -621,14 +638,12 @@ dmwf_status build_ring_tables(dmwf_plan* p) {
         !up((void**)&p->d_ring_blue, blue.data(), nq * sizeof(int)) ||
         !up((void**)&p->d_ring_coff, coff.data(), nq * sizeof(long long)) ||
         !up((void**)&p->d_ring_boff, boff.data(), nq * sizeof(long long)) ||
-        !up((void**)&p->d_twiddle, W.data(), W.size() * sizeof(double2)) ||
         !up((void**)&p->d_chirp, C.data(), C.size() * sizeof(double2)) ||
         !up((void**)&p->d_ring_class, all.data(), all.size() * sizeof(int)) ||
         hipMalloc((void**)&p->d_bspec, std::max<long long>(bsum, 1) * sizeof(double2)) != hipSuccess) {
         set_error("allocation or upload of ring FFT tables failed");
         return DMWF_ERR_OOM;
     }
-    p->twiddle_log = wlog;
     // filter spectra, one class at a time
     std::vector<int> bl[kRingClasses];
     for (int q = 0; q < nq; ++q)
@@ -643,7 +658,7 @@ dmwf_status build_ring_tables(dmwf_plan* p) {
         const size_t lds = class_lds(c);
         hipLaunchKernelGGL((k_chirp_spectrum<512>), dim3(bl[c].size()), dim3(512), lds, nullptr, dq,
                            p->d_nph, p->d_ring_M, p->d_ring_coff, p->d_ring_boff, p->d_chirp,
-                           p->d_bspec, p->d_twiddle, wlog);
+                           p->d_bspec);
         DMWF_HIP(hipGetLastError());
         DMWF_HIP(hipDeviceSynchronize());
         DMWF_HIP(hipFree(dq));
@@ -669,8 +684,6 @@ dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const int* e
     a.blue = p->d_ring_blue;
     a.coff = p->d_ring_coff;
     a.boff = p->d_ring_boff;
-    a.W = p->d_twiddle;
-    a.wlog = p->twiddle_log;
     a.chirp = p->d_chirp;
     a.bspec = p->d_bspec;
     int cls = PROF_RING_ANA;
