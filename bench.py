@@ -93,12 +93,64 @@ def cpu_baseline(nside, lmax, iters_per_solve, fraction):
         "unit": "solves/s",
         "cores": oracle.max_threads(),
         "kind": "oracle",
-        "sample": (f"FP64 oracle synthesis on every {k}th ring and adjoint on every {k}th m at "
-                   f"Nside {nside}, lmax {lmax} ({t2 - t0:.1f} s), scaled by the exact work ratio "
-                   f"to one full-band pair ({pair_s:.1f} s) and by the {iters_per_solve} "
-                   f"iterations of the GPU solve"),
+        "sample": ((f"one full-band FP64 oracle pair (synthesis on all rings, adjoint on all m) "
+                    if k == 1 else
+                    f"FP64 oracle synthesis on every {k}th ring and adjoint on every {k}th m, scaled "
+                    f"by the exact work ratio to one full-band pair, ")
+                   + f"at Nside {nside}, lmax {lmax}: {t2 - t0:.1f} s measured, {pair_s:.1f} s per "
+                   f"pair, times the {iters_per_solve} iterations of the GPU solve"),
         "pair_seconds": pair_s,
     }
+
+
+TRAFFIC_FILES = {
+    "legendre_analysis": ("profiles/k_leg_ana_cfg3_nside1024_hbm_traffic.md",
+                          "paper_1702_08852_amd/csrc/legendre.hip"),
+    "legendre_synthesis": ("profiles/k_leg_syn_cfg3_nside1024_hbm_traffic.md",
+                           "paper_1702_08852_amd/csrc/legendre.hip"),
+}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary of this kernel.
+
+    The summary holds a line 'traffic_json: {...}' with the calibrated bytes per
+    launch and the SHA-256 of the kernel's source file at the time the counters
+    were taken; if the source has changed since, the figure no longer describes
+    the kernel and None is returned.
+    """
+    import hashlib
+
+    ent = TRAFFIC_FILES.get(kernel)
+    if ent is None:
+        return None
+    summ, src = (os.path.join(ROOT, x) for x in ent)
+    if not (os.path.exists(summ) and os.path.exists(src)):
+        return None
+    rec = None
+    for line in open(summ):
+        if line.startswith("traffic_json:"):
+            rec = json.loads(line.split(":", 1)[1])
+    if rec is None:
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec["bytes_per_launch"]
+
+
+def copy_calibration(dev):
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters (reads and writes 2^30 bytes per launch)."""
+    import torch
+
+    n = (1 << 30) // 8
+    src = torch.rand(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.mul(src, 1.0, out=dst)  # an elementwise kernel, not a runtime blit
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": 1 << 30, "launches": 5}))
 
 
 def main():
@@ -108,8 +160,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nside", type=int, default=1024)
     ap.add_argument("--pairs", type=int, default=10, help="full-band iterations timed separately")
-    ap.add_argument("--cpu-fraction", type=float, default=0.25)
+    ap.add_argument("--cpu-fraction", type=float, default=1.0,
+                    help="fraction of rings (synthesis) and of m (adjoint) the oracle evaluates")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -119,6 +174,9 @@ def main():
     import torch
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        copy_calibration(dev)
+        return
     nside = args.nside
     p, plan, cl, d, w, np = make_inputs(nside, dev)
     lmax = p.lmax
@@ -157,7 +215,7 @@ def main():
         achieved = leg_flops / (tot_ms * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": achieved,
                 "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+                "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": measured_traffic(dom),
                 "launches": cnt, "avg_launch_ms": tot_ms / cnt}
     else:
         npix = 12 * nside * nside
