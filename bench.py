@@ -167,8 +167,8 @@ def main():
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "layout is described in DESIGN.md and not implemented.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this library "
+              "has no multi-GPU path (no collectives, no sharding).", file=sys.stderr)
         sys.exit(2)
 
     import torch

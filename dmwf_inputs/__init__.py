@@ -11,7 +11,7 @@ code.  The data map d = Y a + n needs a synthesis Y; the caller supplies it
 The paper's only experiment uses a CAMB spectrum on a flat 512^2 patch
 (Section 3), which is not reproduced here.  These recipes stand in for it on
 the sphere: an analytic C_l, inhomogeneous noise and a galactic cut plus point
-source holes, with the sizes of the configurations documented in the design doc.
+source holes, at the sizes of the three single-map configurations below.
 
 Every draw is reproducible from (config id, map index, stream name).
 """

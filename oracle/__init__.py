@@ -13,7 +13,7 @@ Contents
             (small Nside only), and the fixed point of one cooling level
 
 Every routine is FP64.  Where the paper is silent or ambiguous the reading
-taken is listed in the design doc and repeated in the docstring concerned.
+taken is stated in the docstring concerned.
 """
 from __future__ import annotations
 

@@ -14,7 +14,7 @@ Each cooling level repeats two diagonal solves,
 
 until the Cauchy ratio ||s_i - s_{i-1}|| / ||s_i|| drops below epsilon.
 
-Readings on the sphere (each listed in the design doc):
+Readings on the sphere:
   * F^-1 = Y (synthesis), F = Omega Y^H with Omega = 4 pi / Npix the pixel
     area, so sigma = 1/Omega; mu is in harmonic units, mu = (xi-alpha)/sigma,
     and the harmonic messenger variance is xi/sigma.

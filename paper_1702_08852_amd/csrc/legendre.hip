@@ -278,31 +278,63 @@ struct AnaArgs {
     int lmax, nq, lp;
 };
 
-// Eight even/odd pairs (16 l) accumulating the lane's K rings into acc[].
+// The recurrence table viewed in the constant address space: with a
+// wave-uniform index its loads become scalar loads even in a loop that also
+// stores (to LDS and to the partial sums).
+typedef const __attribute__((address_space(4))) double* const_dptr;
+
+// Cross-lane sums through the lane-swap instructions (no LDS).  xsum32(a, b):
+// lanes 0..31 return a_i + a_{i+32}, lanes 32..63 return b_{i-32} + b_i.
+__device__ __forceinline__ double xsum32(double a, double b) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false,
+                                                     false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false,
+                                                     false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+// Sum of v over the four lanes i, i ^ 16, i ^ 32, i ^ 48, returned in all four.
+__device__ __forceinline__ double xsum_rows(double v) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false,
+                                                     false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false,
+                                                     false);
+    v = __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+    return xsum32(v, v);
+}
+
+// Row of the analysis reduction buffer: 64 lanes' values with one pad slot
+// after lane 31, so that the upper half starts 4 banks after the lower and
+// rows are 8 banks apart (66 double2 = 264 dwords).
+constexpr int kRedRow = 66;
+
+// Eight even/odd pairs (16 l) of the lane's K rings.  Pair j leaves through
+// red[j][.]: lanes 0..31 hold the even l0 + 2j summed over lanes i and i+32,
+// lanes 32..63 the odd l0 + 2j + 1.
 template <int K, bool INJ>
 __device__ __forceinline__ void ana_block(int l0, const double* __restrict__ A,
                                           const double (&x)[K], double (&p1)[K], double (&p2)[K],
                                           const double (&gpr)[K], const double (&gpi)[K],
                                           const double (&gmr)[K], const double (&gmi)[K],
-                                          const int (&ls)[K], const double (&s0)[K],
-                                          const double (&s1)[K], double (&accr)[kAnaB],
-                                          double (&acci)[kAnaB]) {
+                                          const int (&rel)[K], const double (&s0)[K],
+                                          const double (&s1)[K], double2 (*red)[kRedRow],
+                                          int lane) {
 #pragma unroll
     for (int j = 0; j < kAnaB / 2; ++j) {
         const int l = l0 + 2 * j;
-        const double Ae = A[l], Ao = A[l + 1];
+        const double Ae = ((const_dptr)A)[l], Ao = ((const_dptr)A)[l + 1];
         double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;
 #pragma unroll
         for (int t = 0; t < K; ++t) {
             double ue = fma(Ae * x[t], p1[t], -p2[t]);
-            if (INJ && l == ls[t]) {
+            if (INJ && rel[t] == 2 * j) {
                 ue = s1[t];
                 p1[t] = s0[t];
             }
             er = fma(ue, gpr[t], er);
             ei = fma(ue, gpi[t], ei);
             double uo = fma(Ao * x[t], ue, -p1[t]);
-            if (INJ && l + 1 == ls[t]) {
+            if (INJ && rel[t] == 2 * j + 1) {
                 uo = s1[t];
                 ue = s0[t];
             }
@@ -311,10 +343,7 @@ __device__ __forceinline__ void ana_block(int l0, const double* __restrict__ A,
             p2[t] = ue;
             p1[t] = uo;
         }
-        accr[2 * j] = er;
-        acci[2 * j] = ei;
-        accr[2 * j + 1] = orr;
-        acci[2 * j + 1] = oi;
+        red[j][lane + (lane >> 5)] = make_double2(xsum32(er, orr), xsum32(ei, oi));
     }
 }
 
@@ -327,12 +356,12 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 template <int K>
 __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
-    __shared__ double2 red_all[kLegWaves][kAnaB][65];
+    __shared__ double2 red_all[kLegWaves][kAnaB / 2][kRedRow];
     const int w = threadIdx.x >> 6;
     const int m = __builtin_amdgcn_readfirstlane(blockIdx.y * kLegWaves + w);
     const int ell = *a.ell;
     if (m > ell) return;
-    double2 (*red)[65] = red_all[w];
+    double2 (*red)[kRedRow] = red_all[w];
     const int lane = threadIdx.x & 63;
     const int nq = a.nq;
     const int q0 = blockIdx.x * (64 * K) + lane;
@@ -378,30 +407,31 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
     const double* A = a.A + base;
     const int L0 = m + ((lo - m) & ~1);
     for (int l = m + lane; l < L0; l += 64) out[l] = make_double2(0.0, 0.0);
-    // lane reads row rb = lane & 15 (sixteen rows in distinct banks per
-    // 16-lane group), part rp = lane >> 4; parts combine across lanes 16 apart
+    // lane sums eight of the 32 half-sums of l0 + rb: row rb >> 1, half rb & 1,
+    // part rp = lane >> 4; the four parts then combine across lanes 16 apart
     const int rb = lane & 15, rp = lane >> 4;
+    const int rcol = (rb & 1) * 33 + rp * 8;
     for (int l0 = L0; l0 <= ell; l0 += kAnaB) {
-        double accr[kAnaB], acci[kAnaB];
-        if (l0 <= hi)
-            ana_block<K, true>(l0, A, x, p1, p2, gpr, gpi, gmr, gmi, ls, s0, s1, accr, acci);
-        else
-            ana_block<K, false>(l0, A, x, p1, p2, gpr, gpi, gmr, gmi, ls, s0, s1, accr, acci);
+        if (l0 <= hi) {
+            // start of each ring relative to this block (compile-time offsets
+            // in the comparisons keep them out of registers)
+            int rel[K];
 #pragma unroll
-        for (int b = 0; b < kAnaB; ++b) red[b][lane] = make_double2(accr[b], acci[b]);
+            for (int t = 0; t < K; ++t) rel[t] = ls[t] - l0;
+            ana_block<K, true>(l0, A, x, p1, p2, gpr, gpi, gmr, gmi, rel, s0, s1, red, lane);
+        } else
+            ana_block<K, false>(l0, A, x, p1, p2, gpr, gpi, gmr, gmi, ls, s0, s1, red, lane);
         wave_lds_sync();
         double sr = 0.0, si = 0.0;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const double2 v = red[rb][rp * 16 + i];
+        for (int i = 0; i < 8; ++i) {
+            const double2 v = red[rb >> 1][rcol + i];
             sr += v.x;
             si += v.y;
         }
-        sr += __shfl_xor(sr, 16);
-        si += __shfl_xor(si, 16);
-        sr += __shfl_xor(sr, 32);
-        si += __shfl_xor(si, 32);
         wave_lds_sync();
+        sr = xsum_rows(sr);
+        si = xsum_rows(si);
         if (rp == 0 && l0 + rb <= ell) out[l0 + rb] = make_double2(sr, si);
     }
 }

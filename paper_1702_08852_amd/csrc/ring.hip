@@ -9,9 +9,10 @@
 //              H_k = sum_{m = k mod n} F_m e^{i m phi0}   (aliasing fold, F_{-m} = conj F_m)
 //   analysis   G_m = e^{-i m phi0} R_{m mod n},  R_k = sum_j r_j w^{-jk},  w = e^{2 pi i/n}.
 //
-// The length-n DFTs run in LDS: an in-place radix-2 decimation-in-time FFT on
-// bit-reversed input with up to three stages fused per pass in registers.
-// Ring lengths that are not powers of two (polar rings, n = 4i) use
+// The length-n DFTs run in LDS (padded against bank conflicts) as Stockham
+// passes of radix 16 with twiddles computed in registers, and one pass of a
+// smaller radix for the remaining bits; each radix-R butterfly is an
+// in-register radix-2 DFT of R points.  Ring lengths that are not powers of two (polar rings, n = 4i) use
 // Bluestein's chirp-z identity jk = (j^2 + k^2 - (k-j)^2)/2, which turns the
 // DFT into a cyclic convolution of length M >= 2n-1 (a power of two) with the
 // chirp c_t = e^{i pi t^2/n}; the spectrum of the chirp filter is a plan table.
