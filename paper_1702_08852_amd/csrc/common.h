@@ -26,8 +26,9 @@ namespace dmwf {
 constexpr int kSynK = DMWF_SYN_K;
 constexpr int kAnaK = DMWF_ANA_K;
 constexpr int kLegWaves = DMWF_LEG_WAVES;
-// l values per analysis reduction block.
-constexpr int kAnaB = 16;
+// l values per block of the Legendre kernels: recurrences start only at the
+// first l of a block (counted from m), and the analysis reduces once per block.
+constexpr int kLegB = 16;
 // Padding (entries) after the per-(l,m) tables so that look-ahead reads of
 // the recurrence coefficients stay inside the allocation.
 constexpr int kTablePad = 64;

@@ -65,8 +65,15 @@ __global__ void k_seed_mm(int lmax, int nq, const double* __restrict__ sint,
     }
 }
 
-// Walk the recurrence up from l = m until |lambda_lm| >= 2^kSkipLog2; record
-// that l and mu_{l-1}, mu_l (true scale).  kNever if it is not reached by lmax.
+// Walk the recurrence up from l = m until |lambda_lm| >= 2^kSkipLog2 at some
+// l = ls.  The Legendre kernels start a ring at the first l of the 16-l block
+// (counted from m) that holds ls, ls_a = m + 16 floor((ls - m) / 16), so that
+// starts only happen at block boundaries; record ls_a and the pair (p2, p1)
+// from which the recurrence's first step there yields mu_{ls_a}:
+// (mu_{ls_a - 2}, mu_{ls_a - 1}), or (-mu_m, 0) when ls_a = m (A_m = 0).
+// The terms between ls_a and ls are below the threshold but kept: each step
+// grows |lambda| by at most about sqrt(2 lmax) there, so 15 steps back stay
+// far inside the FP64 range.  kNever if ls is not reached by lmax.
 __global__ void k_seed_up(int lmax, int nq, const double* __restrict__ xs,
                           const double* __restrict__ A, const double* __restrict__ g,
                           const double* __restrict__ mant, const int* __restrict__ expo,
@@ -81,28 +88,35 @@ __global__ void k_seed_up(int lmax, int nq, const double* __restrict__ xs,
     const double thr = ldexp(1.0, kSkipLog2);
     double cur = mant[o], prev = 0.0;
     int e = expo[o];
-    int l = m;
-    if (!(ldexp(fabs(g[base + l] * cur), e) >= thr)) {
-        for (l = m + 1; l <= lmax; ++l) {
-            const double nx = fma(A[base + l] * x, cur, -prev);
-            prev = cur;
-            cur = nx;
-            if (fabs(cur) > 0x1p256) {
-                cur = ldexp(cur, -256);
-                prev = ldexp(prev, -256);
-                e += 256;
-            }
-            if (ldexp(fabs(g[base + l] * cur), e) >= thr) break;
+    // state at the start of the current block: (p2, p1) scaled by 2^se
+    double sp2 = -cur, sp1 = 0.0;
+    int se = e, la = m;
+    bool hit = ldexp(fabs(g[base + m] * cur), e) >= thr;
+    for (int l = m + 1; !hit && l <= lmax; ++l) {
+        if (((l - m) % kLegB) == 0) {
+            sp2 = prev;
+            sp1 = cur;
+            se = e;
+            la = l;
         }
+        const double nx = fma(A[base + l] * x, cur, -prev);
+        prev = cur;
+        cur = nx;
+        if (fabs(cur) > 0x1p256) {
+            cur = ldexp(cur, -256);
+            prev = ldexp(prev, -256);
+            e += 256;
+        }
+        hit = ldexp(fabs(g[base + l] * cur), e) >= thr;
     }
-    if (l > lmax) {
+    if (!hit) {
         ls_out[o] = kNever;
         s0_out[o] = 0.0;
         s1_out[o] = 0.0;
     } else {
-        ls_out[o] = l;
-        s0_out[o] = ldexp(prev, e);
-        s1_out[o] = ldexp(cur, e);
+        ls_out[o] = la;
+        s0_out[o] = ldexp(sp2, se);
+        s1_out[o] = ldexp(sp1, se);
     }
 }
 
@@ -157,38 +171,40 @@ struct SynArgs {
 };
 
 // One even/odd pair of recurrence steps (l even offset from m, l+1 odd) for
-// the K rings of a lane.  With INJ the lanes whose start is l or l+1 load
-// their stored (mu_{ls-1}, mu_ls) there.
-template <int K, bool INJ>
+// the K rings of a lane.
+template <int K>
 __device__ __forceinline__ void syn_pair(int l, bool odd_live, const double* __restrict__ A,
                                          const double2* __restrict__ ap, const double (&x)[K],
                                          double (&p1)[K], double (&p2)[K], double (&er)[K],
-                                         double (&ei)[K], double (&orr)[K], double (&oi)[K],
-                                         const int (&ls)[K], const double (&s0)[K],
-                                         const double (&s1)[K]) {
+                                         double (&ei)[K], double (&orr)[K], double (&oi)[K]) {
     const double Ae = A[l], Ao = A[l + 1];
     const double2 ce = ap[l];
     double2 co = ap[l + 1];
     if (!odd_live) co = make_double2(0.0, 0.0);
 #pragma unroll
     for (int t = 0; t < K; ++t) {
-        double ue = fma(Ae * x[t], p1[t], -p2[t]);
-        if (INJ && l == ls[t]) {
-            ue = s1[t];
-            p1[t] = s0[t];
-        }
+        const double ue = fma(Ae * x[t], p1[t], -p2[t]);
         er[t] = fma(ue, ce.x, er[t]);
         ei[t] = fma(ue, ce.y, ei[t]);
-        double uo = fma(Ao * x[t], ue, -p1[t]);
-        if (INJ && l + 1 == ls[t]) {
-            uo = s1[t];
-            ue = s0[t];
-        }
+        const double uo = fma(Ao * x[t], ue, -p1[t]);
         orr[t] = fma(uo, co.x, orr[t]);
         oi[t] = fma(uo, co.y, oi[t]);
         p2[t] = ue;
         p1[t] = uo;
     }
+}
+
+// Rings whose recurrence starts at block l take their seed pair; the others
+// either run already or still hold (0, 0) and contribute nothing.
+template <int K>
+__device__ __forceinline__ void inject(int l, const int (&ls)[K], const double (&s0)[K],
+                                       const double (&s1)[K], double (&p1)[K], double (&p2)[K]) {
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+        if (ls[t] == l) {
+            p2[t] = s0[t];
+            p1[t] = s1[t];
+        }
 }
 
 template <int K>
@@ -234,16 +250,18 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn(SynArgs a) {
         const long long base = alm_base(m, a.lmax);
         const double* A = a.A + base;
         const double2* ap = a.ap + base;
-        int l = m + ((lo - m) & ~1);
-        for (; l <= hi; l += 2)
-            syn_pair<K, true>(l, l + 1 <= ell, A, ap, x, p1, p2, er, ei, orr, oi, ls, s0, s1);
-        for (; l + 15 <= ell; l += 16) {
+        // every start is the first l of a 16-l block counted from m
+        int l = lo;
+        for (; l + kLegB - 1 <= ell; l += kLegB) {
+            if (l <= hi) inject<K>(l, ls, s0, s1, p1, p2);
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                syn_pair<K, false>(l + 2 * j, true, A, ap, x, p1, p2, er, ei, orr, oi, ls, s0, s1);
+            for (int j = 0; j < kLegB / 2; ++j)
+                syn_pair<K>(l + 2 * j, true, A, ap, x, p1, p2, er, ei, orr, oi);
         }
-        for (; l <= ell; l += 2)
-            syn_pair<K, false>(l, l + 1 <= ell, A, ap, x, p1, p2, er, ei, orr, oi, ls, s0, s1);
+        if (l <= ell) {
+            if (l <= hi) inject<K>(l, ls, s0, s1, p1, p2);
+            for (; l <= ell; l += 2) syn_pair<K>(l, l + 1 <= ell, A, ap, x, p1, p2, er, ei, orr, oi);
+        }
     }
 #pragma unroll
     for (int t = 0; t < K; ++t) {
@@ -311,33 +329,23 @@ constexpr int kRedRow = 66;
 // Eight even/odd pairs (16 l) of the lane's K rings.  Pair j leaves through
 // red[j][.]: lanes 0..31 hold the even l0 + 2j summed over lanes i and i+32,
 // lanes 32..63 the odd l0 + 2j + 1.
-template <int K, bool INJ>
+template <int K>
 __device__ __forceinline__ void ana_block(int l0, const double* __restrict__ A,
                                           const double (&x)[K], double (&p1)[K], double (&p2)[K],
                                           const double (&gpr)[K], const double (&gpi)[K],
                                           const double (&gmr)[K], const double (&gmi)[K],
-                                          const int (&rel)[K], const double (&s0)[K],
-                                          const double (&s1)[K], double2 (*red)[kRedRow],
-                                          int lane) {
+                                          double2 (*red)[kRedRow], int lane) {
 #pragma unroll
-    for (int j = 0; j < kAnaB / 2; ++j) {
+    for (int j = 0; j < kLegB / 2; ++j) {
         const int l = l0 + 2 * j;
         const double Ae = ((const_dptr)A)[l], Ao = ((const_dptr)A)[l + 1];
         double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;
 #pragma unroll
         for (int t = 0; t < K; ++t) {
-            double ue = fma(Ae * x[t], p1[t], -p2[t]);
-            if (INJ && rel[t] == 2 * j) {
-                ue = s1[t];
-                p1[t] = s0[t];
-            }
+            const double ue = fma(Ae * x[t], p1[t], -p2[t]);
             er = fma(ue, gpr[t], er);
             ei = fma(ue, gpi[t], ei);
-            double uo = fma(Ao * x[t], ue, -p1[t]);
-            if (INJ && rel[t] == 2 * j + 1) {
-                uo = s1[t];
-                ue = s0[t];
-            }
+            const double uo = fma(Ao * x[t], ue, -p1[t]);
             orr = fma(uo, gmr[t], orr);
             oi = fma(uo, gmi[t], oi);
             p2[t] = ue;
@@ -356,7 +364,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 template <int K>
 __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
-    __shared__ double2 red_all[kLegWaves][kAnaB / 2][kRedRow];
+    __shared__ double2 red_all[kLegWaves][kLegB / 2][kRedRow];
     const int w = threadIdx.x >> 6;
     const int m = __builtin_amdgcn_readfirstlane(blockIdx.y * kLegWaves + w);
     const int ell = *a.ell;
@@ -405,22 +413,16 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
         return;
     }
     const double* A = a.A + base;
-    const int L0 = m + ((lo - m) & ~1);
+    // every start is the first l of a 16-l block counted from m
+    const int L0 = lo;
     for (int l = m + lane; l < L0; l += 64) out[l] = make_double2(0.0, 0.0);
     // lane sums eight of the 32 half-sums of l0 + rb: row rb >> 1, half rb & 1,
     // part rp = lane >> 4; the four parts then combine across lanes 16 apart
     const int rb = lane & 15, rp = lane >> 4;
     const int rcol = (rb & 1) * 33 + rp * 8;
-    for (int l0 = L0; l0 <= ell; l0 += kAnaB) {
-        if (l0 <= hi) {
-            // start of each ring relative to this block (compile-time offsets
-            // in the comparisons keep them out of registers)
-            int rel[K];
-#pragma unroll
-            for (int t = 0; t < K; ++t) rel[t] = ls[t] - l0;
-            ana_block<K, true>(l0, A, x, p1, p2, gpr, gpi, gmr, gmi, rel, s0, s1, red, lane);
-        } else
-            ana_block<K, false>(l0, A, x, p1, p2, gpr, gpi, gmr, gmi, ls, s0, s1, red, lane);
+    for (int l0 = L0; l0 <= ell; l0 += kLegB) {
+        if (l0 <= hi) inject<K>(l0, ls, s0, s1, p1, p2);
+        ana_block<K>(l0, A, x, p1, p2, gpr, gpi, gmr, gmi, red, lane);
         wave_lds_sync();
         double sr = 0.0, si = 0.0;
 #pragma unroll
