@@ -184,65 +184,76 @@ __device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int M, 
 }
 
 // Forward DFT of length M = 2^logM in place, natural order in and out:
-// radix-RMAX passes while enough bits remain, then one pass of a smaller
-// radix with up to 16 values per thread.
-template <int RMAX>
-__device__ __forceinline__ void fft(double2* buf, int M, int logM, int tid, int nt) {
-    constexpr int LR = ilog2(RMAX);
-    int left = logM, Ns = 1;
-    while (left >= LR) {
-        const int nb = M >> LR;
-        if (nb > nt) stockham_pass<RMAX, (RMAX == 16 ? 1 : 2)>(buf, M, Ns, tid, nt);
-        else stockham_pass<RMAX, 1>(buf, M, Ns, tid, nt);
-        Ns <<= LR;
-        left -= LR;
+// radix-16 passes while four or more bits remain, then one pass of radix 8,
+// 4 or 2.  MFIX > 0 fixes M at compile time (one code path per launch
+// class), MFIX = 0 takes it at run time.  Radix-16 passes keep one butterfly
+// per thread, which needs M / 16 <= NT.
+template <int NT, int MFIX>
+__device__ __forceinline__ void fft(double2* buf, int M, int logM, int tid) {
+    static_assert(MFIX == 0 || MFIX / 16 <= NT, "one radix-16 butterfly per thread");
+    // opaque copy of the thread index: keeps the passes' LDS addresses from
+    // being hoisted out of the caller's loop into long-lived registers
+    asm volatile("" : "+v"(tid));
+    const int lm = MFIX > 0 ? ilog2(MFIX) : logM;
+    int Ns = 1;
+#pragma unroll 1
+    for (int p = 0; p < (lm >> 2); ++p) {
+        stockham_pass<16, 1>(buf, M, Ns, tid, NT);
+        Ns <<= 4;
     }
-    if (left > 0) {
-        const int nb = M >> left;
-        const int bpt = nb > nt ? nb / nt : 1;
-        if (left == 3) {
-            if (bpt == 1) stockham_pass<8, 1>(buf, M, Ns, tid, nt);
-            else stockham_pass<8, 2>(buf, M, Ns, tid, nt);
-        } else if (left == 2) {
-            if (bpt == 1) stockham_pass<4, 1>(buf, M, Ns, tid, nt);
-            else if (bpt == 2) stockham_pass<4, 2>(buf, M, Ns, tid, nt);
-            else stockham_pass<4, 4>(buf, M, Ns, tid, nt);
-        } else {
-            if (bpt == 1) stockham_pass<2, 1>(buf, M, Ns, tid, nt);
-            else if (bpt == 2) stockham_pass<2, 2>(buf, M, Ns, tid, nt);
-            else if (bpt == 4) stockham_pass<2, 4>(buf, M, Ns, tid, nt);
-            else stockham_pass<2, 8>(buf, M, Ns, tid, nt);
+    if constexpr (MFIX > 0) {
+        constexpr int L = ilog2(MFIX) & 3;
+        constexpr int NB = MFIX >> L;
+        constexpr int BPT = NB > NT ? NB / NT : 1;
+        if constexpr (L == 3) stockham_pass<8, BPT>(buf, M, Ns, tid, NT);
+        else if constexpr (L == 2) stockham_pass<4, BPT>(buf, M, Ns, tid, NT);
+        else if constexpr (L == 1) stockham_pass<2, BPT>(buf, M, Ns, tid, NT);
+    } else {
+        const int left = lm & 3;
+        if (left > 0) {
+            const int nb = M >> left;
+            const int bpt = nb > NT ? nb / NT : 1;
+            if (left == 3) {
+                if (bpt == 1) stockham_pass<8, 1>(buf, M, Ns, tid, NT);
+                else stockham_pass<8, 2>(buf, M, Ns, tid, NT);
+            } else if (left == 2) {
+                if (bpt == 1) stockham_pass<4, 1>(buf, M, Ns, tid, NT);
+                else if (bpt == 2) stockham_pass<4, 2>(buf, M, Ns, tid, NT);
+                else stockham_pass<4, 4>(buf, M, Ns, tid, NT);
+            } else {
+                if (bpt == 1) stockham_pass<2, 1>(buf, M, Ns, tid, NT);
+                else if (bpt == 2) stockham_pass<2, 2>(buf, M, Ns, tid, NT);
+                else if (bpt == 4) stockham_pass<2, 4>(buf, M, Ns, tid, NT);
+                else stockham_pass<2, 8>(buf, M, Ns, tid, NT);
+            }
         }
     }
 }
 
-// buf holds a (natural order, zero-padded to M).  Leaves buf_k = conj(conv_k),
-// conv = a (*) b the cyclic convolution of length M, so the length-n forward
-// DFT of the chirped input is X_k = conj(c_k buf_k).
-template <int RMAX>
-__device__ __forceinline__ void bluestein(double2* buf, int M, int logM, const double2* __restrict__ B,
-                                          int tid, int nt) {
-    fft<RMAX>(buf, M, logM, tid, nt);
+// Middle step of Bluestein's algorithm: buf = FFT_M(a) on entry; leaves
+// conj(buf B) / M, whose forward FFT is conj(M conv), conv = a (*) b the
+// cyclic convolution of length M (B = FFT_M(b) from the plan).
+template <int NT>
+__device__ __forceinline__ void filter_product(double2* buf, int M, const double2* __restrict__ B,
+                                               int tid) {
     const double inv = 1.0 / M;
     // eight filter values in flight per thread before they are used
-    for (int k0 = tid; k0 < M; k0 += 8 * nt) {
+    for (int k0 = tid; k0 < M; k0 += 8 * NT) {
         double2 b[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int k = k0 + u * nt;
+            const int k = k0 + u * NT;
             b[u] = k < M ? B[k] : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int k = k0 + u * nt;
+            const int k = k0 + u * NT;
             if (k < M) {
                 const double2 ak = cmul(buf[pad(k)], b[u]);
                 buf[pad(k)] = make_double2(ak.x * inv, -ak.y * inv);
             }
         }
     }
-    __syncthreads();
-    fft<RMAX>(buf, M, logM, tid, nt);
 }
 
 template <int NT>
@@ -261,7 +272,25 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
     return t;
 }
 
-template <int NT, int J, int RMAX>
+// Analysis input z_j = r^N_j + i r^S_j [times conj(c_j) for Bluestein rings],
+// zero-padded to M.
+template <int NT, int J>
+__device__ __forceinline__ void ana_input(double2* buf, const double (&rn)[J],
+                                          const double (&rs)[J], int n, int M, bool blue,
+                                          const double2* __restrict__ ch, int tid) {
+#pragma unroll
+    for (int t = 0; t < J; ++t) {
+        const int j = tid + t * NT;
+        if (j < n) {
+            double2 z = make_double2(rn[t], rs[t]);
+            if (blue) z = cmul(z, conj2(ch[j]));
+            buf[pad(j)] = z;
+        }
+    }
+    for (int j = n + tid; j < M; j += NT) buf[pad(j)] = make_double2(0.0, 0.0);
+}
+
+template <int NT, int J, int MFIX>
 __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     extern __shared__ double2 buf[];
     __shared__ double red[NT / 64];
@@ -359,8 +388,49 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
             }
             __syncthreads();
         }
-        if (blue) bluestein<RMAX>(buf, M, logM, B, tid, NT);
-        else fft<RMAX>(buf, M, logM, tid, NT);
+    } else {
+        // analysis only: the input comes from the pixels
+#pragma unroll
+        for (int t = 0; t < J; ++t) {
+            const int j = tid + t * NT;
+            rn[t] = 0.0;
+            rs[t] = 0.0;
+            if (j >= n) continue;
+            for (int h = 0; h < (eq ? 1 : 2); ++h) {
+                const long long p = (h == 0 ? st0 : st1) + j;
+                double v;
+                switch (a.pix) {
+                    case PIX_FIRST: v = a.io.w[p] > 0.0 ? a.io.d[p] : 0.0; break;
+                    case PIX_WRES: v = a.io.w[p] * (a.io.d[p] - a.io.map_in[p]); break;
+                    case PIX_WD: v = a.io.w[p] * a.io.d[p]; break;
+                    case PIX_CRES: {
+                        const double w = a.io.w[p];
+                        const double cc = a.io.xi * w / fma(a.io.xi - a.io.alpha, w, 1.0);
+                        v = cc * (a.io.d[p] - a.io.map_in[p]);
+                        break;
+                    }
+                    default: v = a.io.map_in[p]; break;
+                }
+                if (h == 0) rn[t] = v;
+                else rs[t] = v;
+            }
+        }
+        ana_input<NT, J>(buf, rn, rs, n, M, blue, ch, tid);
+    }
+    __syncthreads();
+
+    // Each DFT is one FFT, or two around the filter product for Bluestein
+    // rings, written as a loop so that the FFT code appears once per direction
+    // (the kernel's instruction footprint stays within the instruction cache).
+    if (syn) {
+#pragma unroll 1
+        for (int step = 0; step < (blue ? 2 : 1); ++step) {
+            fft<NT, MFIX>(buf, M, logM, tid);
+            if (blue && step == 0) {
+                filter_product<NT>(buf, M, B, tid);
+                __syncthreads();
+            }
+        }
         // y_j = IDFT(Z)_j: blue: c_j buf_j; else conj(buf_j).  s^N = Re y, s^S = Im y.
         // Pixel data are loaded for all of the thread's pixels first, then
         // combined and stored, so the loads of one pixel never wait on the
@@ -431,48 +501,18 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
             }
         }
         if (a.mode == RING_SYN) return;
-    } else {
-#pragma unroll
-        for (int t = 0; t < J; ++t) {
-            const int j = tid + t * NT;
-            rn[t] = 0.0;
-            rs[t] = 0.0;
-            if (j >= n) continue;
-            for (int h = 0; h < (eq ? 1 : 2); ++h) {
-                const long long p = (h == 0 ? st0 : st1) + j;
-                double v;
-                switch (a.pix) {
-                    case PIX_FIRST: v = a.io.w[p] > 0.0 ? a.io.d[p] : 0.0; break;
-                    case PIX_WRES: v = a.io.w[p] * (a.io.d[p] - a.io.map_in[p]); break;
-                    case PIX_WD: v = a.io.w[p] * a.io.d[p]; break;
-                    case PIX_CRES: {
-                        const double w = a.io.w[p];
-                        const double cc = a.io.xi * w / fma(a.io.xi - a.io.alpha, w, 1.0);
-                        v = cc * (a.io.d[p] - a.io.map_in[p]);
-                        break;
-                    }
-                    default: v = a.io.map_in[p]; break;
-                }
-                if (h == 0) rn[t] = v;
-                else rs[t] = v;
-            }
+        __syncthreads();
+        ana_input<NT, J>(buf, rn, rs, n, M, blue, ch, tid);
+        __syncthreads();
+    }
+#pragma unroll 1
+    for (int step = 0; step < (blue ? 2 : 1); ++step) {
+        fft<NT, MFIX>(buf, M, logM, tid);
+        if (blue && step == 0) {
+            filter_product<NT>(buf, M, B, tid);
+            __syncthreads();
         }
     }
-    __syncthreads();
-    // analysis input z_j = r^N_j + i r^S_j [times conj(c_j)] at bit-reversed slots
-#pragma unroll
-    for (int t = 0; t < J; ++t) {
-        const int j = tid + t * NT;
-        if (j < n) {
-            double2 z = make_double2(rn[t], rs[t]);
-            if (blue) z = cmul(z, conj2(ch[j]));
-            buf[pad(j)] = z;
-        }
-    }
-    for (int j = n + tid; j < M; j += NT) buf[pad(j)] = make_double2(0.0, 0.0);
-    __syncthreads();
-    if (blue) bluestein<RMAX>(buf, M, logM, B, tid, NT);
-    else fft<RMAX>(buf, M, logM, tid, NT);
     // Z_k = DFT(z)_k; split the two real rings and unfold to m
     for (int m0 = tid; m0 <= ella; m0 += 4 * NT) {
         double2 ckv[4], ccv[4];
@@ -538,27 +578,21 @@ __global__ __launch_bounds__(NT) void k_chirp_spectrum(const int* __restrict__ q
         buf[pad(t)] = v;
     }
     __syncthreads();
-    fft<16>(buf, M, logM, threadIdx.x, NT);
+    fft<NT, 0>(buf, M, logM, threadIdx.x);
     for (int k = threadIdx.x; k < M; k += NT) bspec[boff[q] + k] = buf[pad(k)];
 }
 
 int ring_class(int M) { return M <= 1024 ? 0 : (M == 2048 ? 1 : (M == 4096 ? 2 : 3)); }
 
-// Threads per class: the FFT keeps at most 16 elements per thread.
-#ifndef DMWF_RING_RMAX
-#define DMWF_RING_RMAX 16
-#endif
-#ifndef DMWF_RING_NT3
-#define DMWF_RING_NT3 512
-#endif
+// Threads per class: one radix-16 butterfly per thread and pass at the
+// largest length of the class; the FFT length is fixed at compile time except
+// in the class of short rings.
 void launch_class(int cls, dim3 grid, size_t lds, hipStream_t s, const RingArgs& a) {
-    constexpr int R = DMWF_RING_RMAX;
-    constexpr int NT3 = DMWF_RING_NT3;
     switch (cls) {
-        case 0: hipLaunchKernelGGL((k_ring_fft<128, 8, R>), grid, dim3(128), lds, s, a); break;
-        case 1: hipLaunchKernelGGL((k_ring_fft<256, 8, R>), grid, dim3(256), lds, s, a); break;
-        case 2: hipLaunchKernelGGL((k_ring_fft<512, 8, R>), grid, dim3(512), lds, s, a); break;
-        default: hipLaunchKernelGGL((k_ring_fft<NT3, 4096 / NT3, R>), grid, dim3(NT3), lds, s, a); break;
+        case 0: hipLaunchKernelGGL((k_ring_fft<128, 8, 0>), grid, dim3(128), lds, s, a); break;
+        case 1: hipLaunchKernelGGL((k_ring_fft<256, 8, 2048>), grid, dim3(256), lds, s, a); break;
+        case 2: hipLaunchKernelGGL((k_ring_fft<512, 8, 4096>), grid, dim3(512), lds, s, a); break;
+        default: hipLaunchKernelGGL((k_ring_fft<512, 8, 8192>), grid, dim3(512), lds, s, a); break;
     }
 }
 
