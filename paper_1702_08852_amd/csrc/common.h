@@ -111,6 +111,12 @@ struct dmwf_plan {
     double2* d_bspec = nullptr;        // FFT_M of the chirp filter, per Bluestein ring
     int* d_ring_class = nullptr;       // q lists of the launch classes, concatenated
     int class_off[5] = {0, 0, 0, 0, 0};
+    // side streams (default priority) on which the smaller launch classes run
+    // concurrently with the largest, forked from and joined to the caller's
+    // stream with events
+    hipStream_t ring_side[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ring_fork = nullptr;
+    hipEvent_t ring_join[3] = {nullptr, nullptr, nullptr};
     dmwf::WsLayout ws;
     // profiling
     bool prof = false;

@@ -256,18 +256,21 @@ __device__ __forceinline__ void filter_product(double2* buf, int M, const double
     }
 }
 
+// Sum of (u, v) over the workgroup, returned in thread 0.
 template <int NT>
-__device__ __forceinline__ double block_sum(double v, double* scratch) {
+__device__ __forceinline__ double2 block_sum2(double u, double v, double2* scratch) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    for (int o = 32; o > 0; o >>= 1) {
+        u += __shfl_xor(u, o);
+        v += __shfl_xor(v, o);
+    }
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) scratch[w] = make_double2(u, v);
     __syncthreads();
-    if (lane == 0) scratch[w] = v;
-    __syncthreads();
-    double t = 0.0;
+    double2 t = make_double2(0.0, 0.0);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int i = 0; i < NT / 64; ++i) t += scratch[i];
+        for (int i = 0; i < NT / 64; ++i) t = cadd(t, scratch[i]);
     }
     return t;
 }
@@ -293,7 +296,7 @@ __device__ __forceinline__ void ana_input(double2* buf, const double (&rn)[J],
 template <int NT, int J, int MFIX>
 __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     extern __shared__ double2 buf[];
-    __shared__ double red[NT / 64];
+    __shared__ double2 red[NT / 64];
     const int q = a.qlist[blockIdx.x];
     const int n = a.g.nph[q];
     const int M = a.Mq[q];
@@ -316,7 +319,9 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
         // with F_{-m} = conj(F_m).  The row of F is read once, coalesced, and
         // scattered: m feeds bin m mod n, and -m feeds bin -m mod n.
         const double2* Fq = a.spec + (size_t)q * a.lp * 2;
-        const bool alias = 2 * ell >= n;
+        // Bins collide when 2 ell > n; at 2 ell = n only m = n/2 meets -m,
+        // which one thread handles alone.
+        const bool alias = 2 * ell > n;
         if (alias) {
             for (int k = tid; k < M; k += NT) buf[pad(k)] = make_double2(0.0, 0.0);
             __syncthreads();
@@ -370,12 +375,13 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
                 } else {
                     double2 v = conj2(zp);
                     if (blue) v = cmul(v, conj2(cpv[u]));
-                    buf[pad(kp)] = v;
                     if (m > 0) {
                         double2 w2 = conj2(zm);
                         if (blue) w2 = cmul(w2, conj2(cmv[u]));
-                        buf[pad(km)] = w2;
+                        if (km == kp) v = cadd(v, w2);
+                        else buf[pad(km)] = w2;
                     }
+                    buf[pad(kp)] = v;
                 }
             }
         }
@@ -493,11 +499,11 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
             }
         }
         if (a.mode == RING_ITER) {
-            const double tn = block_sum<NT>(num, red);
-            const double td = block_sum<NT>(den, red);
+            // red[] is written once per launch: no barrier needed before it
+            const double2 t = block_sum2<NT>(num, den, red);
             if (tid == 0) {
-                a.io.cpart[2 * q] = tn;
-                a.io.cpart[2 * q + 1] = td;
+                a.io.cpart[2 * q] = t.x;
+                a.io.cpart[2 * q + 1] = t.y;
             }
         }
         if (a.mode == RING_SYN) return;
@@ -607,6 +613,11 @@ void free_ring_tables(dmwf_plan* p) {
                     p->d_bspec,  p->d_ring_class};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    for (int i = 0; i < 3; ++i) {
+        if (p->ring_side[i]) (void)hipStreamDestroy(p->ring_side[i]);
+        if (p->ring_join[i]) (void)hipEventDestroy(p->ring_join[i]);
+    }
+    if (p->ring_fork) (void)hipEventDestroy(p->ring_fork);
 }
 
 dmwf_status build_ring_tables(dmwf_plan* p) {
@@ -664,6 +675,11 @@ dmwf_status build_ring_tables(dmwf_plan* p) {
         for (int b = 0; b < nb; ++b) all.push_back(L[start[b % 8] + b / 8]);
     }
     p->class_off[kRingClasses] = (int)all.size();
+    for (int i = 0; i < kRingClasses - 1; ++i) {
+        DMWF_HIP(hipStreamCreateWithFlags(&p->ring_side[i], hipStreamNonBlocking));
+        DMWF_HIP(hipEventCreateWithFlags(&p->ring_join[i], hipEventDisableTiming));
+    }
+    DMWF_HIP(hipEventCreateWithFlags(&p->ring_fork, hipEventDisableTiming));
 
     auto up = [&](void** dst, const void* src, size_t bytes) -> bool {
         if (hipMalloc(dst, bytes) != hipSuccess) return false;
@@ -734,14 +750,26 @@ dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const int* e
         case RING_ANA_WD: a.pix = PIX_WD; break;
         case RING_ANA_CRES: a.pix = PIX_CRES; break;
     }
-    // largest classes first
+    // The largest class runs on the caller's stream, the others on side
+    // streams forked from it, so that all four share the GPU; the caller's
+    // stream then waits for every side stream.
+    ProfScope ps(p, s, cls);
+    DMWF_HIP(hipEventRecord(p->ring_fork, s));
     for (int c = kRingClasses - 1; c >= 0; --c) {
         const int nb = p->class_off[c + 1] - p->class_off[c];
         if (nb == 0) continue;
+        hipStream_t sc = s;
+        if (c < kRingClasses - 1) {
+            sc = p->ring_side[c];
+            DMWF_HIP(hipStreamWaitEvent(sc, p->ring_fork, 0));
+        }
         a.qlist = p->d_ring_class + p->class_off[c];
-        ProfScope ps(p, s, cls);
-        launch_class(c, dim3(nb), class_lds(c), s, a);
+        launch_class(c, dim3(nb), class_lds(c), sc, a);
         DMWF_HIP(hipGetLastError());
+        if (c < kRingClasses - 1) {
+            DMWF_HIP(hipEventRecord(p->ring_join[c], sc));
+            DMWF_HIP(hipStreamWaitEvent(s, p->ring_join[c], 0));
+        }
     }
     return DMWF_OK;
 }
