@@ -14,14 +14,14 @@ namespace dmwf {
 
 // Rings per lane in the Legendre kernels: a wave covers 64*K ring pairs.
 #ifndef DMWF_SYN_K
-#define DMWF_SYN_K 4
+#define DMWF_SYN_K 2
 #endif
 #ifndef DMWF_ANA_K
-#define DMWF_ANA_K 4
+#define DMWF_ANA_K 8
 #endif
 // Waves per Legendre workgroup, each on its own m (consecutive m share a CU).
 #ifndef DMWF_LEG_WAVES
-#define DMWF_LEG_WAVES 4
+#define DMWF_LEG_WAVES 2
 #endif
 constexpr int kSynK = DMWF_SYN_K;
 constexpr int kAnaK = DMWF_ANA_K;
