@@ -155,6 +155,18 @@ __global__ void k_mhi(int lmax, int nq, const int* __restrict__ lsmin, const int
     mhi[q] = lo;
 }
 
+// Workgroup b of a 1-D grid runs on XCD b mod 8 (round-robin dispatch).  Give
+// each XCD whole m-groups, all ring chunks of a group together, so that the
+// group's coefficient rows are fetched into a single L2; groups in order of
+// decreasing work (increasing m) within every XCD.
+struct LegTile {
+    int chunk, group;
+};
+__device__ __forceinline__ LegTile leg_tile(int nchunk) {
+    const int b = blockIdx.x, xcd = b & 7, slot = b >> 3;
+    return {slot % nchunk, (slot / nchunk) * 8 + xcd};
+}
+
 // ---------------------------------------------------------------------------
 // synthesis
 // ---------------------------------------------------------------------------
@@ -169,6 +181,23 @@ struct SynArgs {
     const int* ell;
     int lmax, nq, lp;
 };
+
+// The analysis takes its coefficient row through LDS, kChunk l at a time per
+// wave: each lane fetches one l of the next chunk with a vector load while
+// the current chunk is consumed, and the loop reads the values back as
+// wave-uniform broadcasts.  (Scalar loads issued per block stall every block
+// on their latency: the scalar counter only supports waiting for all
+// outstanding loads, so they cannot be issued ahead.)  The synthesis keeps
+// scalar loads: its workgroups of one m-group share an XCD, so the rows are
+// L2 hits, and it measured faster than LDS staging there.
+constexpr int kChunk = 64;
+
+// Orders this wave's LDS writes before its later LDS reads (and reads before
+// later writes); the other waves of the workgroup use their own LDS region.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
 
 // One even/odd pair of recurrence steps (l even offset from m, l+1 odd) for
 // the K rings of a lane.
@@ -210,40 +239,48 @@ __device__ __forceinline__ void inject(int l, const int (&ls)[K], const double (
 template <int K>
 __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn(SynArgs a) {
     // The waves of a workgroup take consecutive m of the same ring chunk; their
-    // results meet in LDS and leave as whole 128-byte segments of the
-    // ring-major rows of F.
+    // results meet in LDS and leave as whole segments of the ring-major rows
+    // of F.
     __shared__ double2 stage[K][64][kLegWaves][2];
     const int w = threadIdx.x >> 6;
     // wave-uniform; readfirstlane lets the compiler use scalar loads for the
     // per-(l, m) coefficients
-    const int m = __builtin_amdgcn_readfirstlane(blockIdx.y * kLegWaves + w);
+    const LegTile tile = leg_tile((a.nq + 64 * K - 1) / (64 * K));
+    const int m = __builtin_amdgcn_readfirstlane(tile.group * kLegWaves + w);
     const int ell = *a.ell;
-    if (blockIdx.y * kLegWaves > ell) return;  // whole workgroup above the band limit
+    if (tile.group * kLegWaves > ell) return;  // whole workgroup above the band limit
     const bool live = m <= ell;
     const int lane = threadIdx.x & 63;
     const int nq = a.nq;
-    const int q0 = blockIdx.x * (64 * K) + lane;
+    const int q0 = tile.chunk * (64 * K) + lane;
     const size_t mo = (size_t)m * nq;
     double x[K], p1[K], p2[K], er[K], ei[K], orr[K], oi[K], s0[K], s1[K];
     int ls[K];
     int lo = kNever, hi = -1;
+    // all loads first, from clamped (valid) addresses, then the masks: one
+    // memory round trip for the whole prologue
+    const size_t mc = live ? mo : 0;
 #pragma unroll
     for (int t = 0; t < K; ++t) {
-        const int q = q0 + 64 * t;
-        const bool v = live && q < nq;
-        x[t] = v ? a.x[q] : 0.0;
-        int l0 = v ? a.ls[mo + q] : kNever;
+        const int qc = min(q0 + 64 * t, nq - 1);
+        x[t] = a.x[qc];
+        ls[t] = a.ls[mc + qc];
+        s0[t] = a.s0[mc + qc];
+        s1[t] = a.s1[mc + qc];
+    }
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        int l0 = (live && q0 + 64 * t < nq) ? ls[t] : kNever;
         if (l0 > ell) l0 = kNever;
         ls[t] = l0;
         const bool act = l0 != kNever;
-        s0[t] = act ? a.s0[mo + q] : 0.0;
-        s1[t] = act ? a.s1[mo + q] : 0.0;
+        if (!act) s0[t] = s1[t] = 0.0;
         lo = min(lo, l0);
         if (act) hi = max(hi, l0);
         p1[t] = p2[t] = er[t] = ei[t] = orr[t] = oi[t] = 0.0;
     }
     // uniform across the wave after the reduction; say so, so that the
-    // per-l coefficient loads below become scalar loads
+    // loop bounds below live in scalar registers
     lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
     hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
     if (lo <= ell) {
@@ -270,10 +307,10 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn(SynArgs a) {
     }
     __syncthreads();
     constexpr int kSlots = kLegWaves * 2;
-    const int m0 = blockIdx.y * kLegWaves;
+    const int m0 = tile.group * kLegWaves;
     for (int idx = threadIdx.x; idx < K * 64 * kSlots; idx += 64 * kLegWaves) {
         const int slot = idx % kSlots, rr = idx / kSlots;
-        const int q = blockIdx.x * (64 * K) + rr;
+        const int q = tile.chunk * (64 * K) + rr;
         const int mm = m0 + (slot >> 1);
         if (q < nq && mm <= ell)
             a.spec[((size_t)q * a.lp + mm) * 2 + (slot & 1)] = stage[rr >> 6][rr & 63][slot >> 1][slot & 1];
@@ -295,11 +332,6 @@ struct AnaArgs {
     const int* ell;
     int lmax, nq, lp;
 };
-
-// The recurrence table viewed in the constant address space: with a
-// wave-uniform index its loads become scalar loads even in a loop that also
-// stores (to LDS and to the partial sums).
-typedef const __attribute__((address_space(4))) double* const_dptr;
 
 // Cross-lane sums through the lane-swap instructions (no LDS).  xsum32(a, b):
 // lanes 0..31 return a_i + a_{i+32}, lanes 32..63 return b_{i-32} + b_i.
@@ -326,19 +358,20 @@ __device__ __forceinline__ double xsum_rows(double v) {
 // rows are 8 banks apart (66 double2 = 264 dwords).
 constexpr int kRedRow = 66;
 
-// Eight even/odd pairs (16 l) of the lane's K rings.  Pair j leaves through
+// Eight even/odd pairs (16 l) of the lane's K rings, A_l staged at CA[i0..].
+// Pair j leaves through
 // red[j][.]: lanes 0..31 hold the even l0 + 2j summed over lanes i and i+32,
 // lanes 32..63 the odd l0 + 2j + 1.
 template <int K>
-__device__ __forceinline__ void ana_block(int l0, const double* __restrict__ A,
+__device__ __forceinline__ void ana_block(const double* CA, int i0,
                                           const double (&x)[K], double (&p1)[K], double (&p2)[K],
                                           const double (&gpr)[K], const double (&gpi)[K],
                                           const double (&gmr)[K], const double (&gmi)[K],
                                           double2 (*red)[kRedRow], int lane) {
 #pragma unroll
     for (int j = 0; j < kLegB / 2; ++j) {
-        const int l = l0 + 2 * j;
-        const double Ae = ((const_dptr)A)[l], Ao = ((const_dptr)A)[l + 1];
+        const double2 AA = *reinterpret_cast<const double2*>(CA + i0 + 2 * j);
+        const double Ae = AA.x, Ao = AA.y;
         double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;
 #pragma unroll
         for (int t = 0; t < K; ++t) {
@@ -355,59 +388,62 @@ __device__ __forceinline__ void ana_block(int l0, const double* __restrict__ A,
     }
 }
 
-// Orders this wave's LDS writes before its later LDS reads (and reads before
-// later writes); the other waves of the workgroup use their own LDS region.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
 template <int K>
 __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
     __shared__ double2 red_all[kLegWaves][kLegB / 2][kRedRow];
+    __shared__ double coef[kLegWaves][2][kChunk];  // per wave: two chunks of A
     const int w = threadIdx.x >> 6;
-    const int m = __builtin_amdgcn_readfirstlane(blockIdx.y * kLegWaves + w);
+    const LegTile tile = leg_tile((a.nq + 64 * K - 1) / (64 * K));
+    const int m = __builtin_amdgcn_readfirstlane(tile.group * kLegWaves + w);
     const int ell = *a.ell;
     if (m > ell) return;
     double2 (*red)[kRedRow] = red_all[w];
     const int lane = threadIdx.x & 63;
     const int nq = a.nq;
-    const int q0 = blockIdx.x * (64 * K) + lane;
+    const int q0 = tile.chunk * (64 * K) + lane;
     const size_t mo = (size_t)m * nq;
     double x[K], p1[K], p2[K], gpr[K], gpi[K], gmr[K], gmi[K], s0[K], s1[K];
     int ls[K];
     int lo = kNever, hi = -1;
+    // all loads first, from clamped (valid) addresses, then the masks: one
+    // memory round trip for the whole prologue.  G of rings that the ring
+    // stage did not write (beyond their m bound) is loaded but never used.
+    double2 gn[K], gs[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) {
-        const int q = q0 + 64 * t;
-        const bool v = q < nq;
-        x[t] = v ? a.x[q] : 0.0;
-        int l0 = v ? a.ls[mo + q] : kNever;
+        const int qc = min(q0 + 64 * t, nq - 1);
+        x[t] = a.x[qc];
+        ls[t] = a.ls[mo + qc];
+        s0[t] = a.s0[mo + qc];
+        s1[t] = a.s1[mo + qc];
+        const double2* g = a.spec + ((size_t)qc * a.lp + m) * 2;
+        gn[t] = g[0];
+        gs[t] = g[1];
+    }
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        int l0 = q0 + 64 * t < nq ? ls[t] : kNever;
         if (l0 > ell) l0 = kNever;
         ls[t] = l0;
         const bool act = l0 != kNever;
-        s0[t] = act ? a.s0[mo + q] : 0.0;
-        s1[t] = act ? a.s1[mo + q] : 0.0;
-        double2 gn = make_double2(0.0, 0.0), gs = make_double2(0.0, 0.0);
-        if (act) {
-            const double2* g = a.spec + ((size_t)q * a.lp + m) * 2;
-            gn = g[0];
-            gs = g[1];
+        if (!act) {
+            s0[t] = s1[t] = 0.0;
+            gn[t] = gs[t] = make_double2(0.0, 0.0);
         }
-        gpr[t] = gn.x + gs.x;
-        gpi[t] = gn.y + gs.y;
-        gmr[t] = gn.x - gs.x;
-        gmi[t] = gn.y - gs.y;
+        gpr[t] = gn[t].x + gs[t].x;
+        gpi[t] = gn[t].y + gs[t].y;
+        gmr[t] = gn[t].x - gs[t].x;
+        gmi[t] = gn[t].y - gs[t].y;
         lo = min(lo, l0);
         if (act) hi = max(hi, l0);
         p1[t] = p2[t] = 0.0;
     }
     // uniform across the wave after the reduction; say so, so that the
-    // per-l coefficient loads below become scalar loads
+    // loop bounds below live in scalar registers
     lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
     hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
     const long long base = alm_base(m, a.lmax);
-    double2* out = a.part + blockIdx.x * a.part_stride + base;
+    double2* out = a.part + tile.chunk * a.part_stride + base;
     if (lo > ell) {
         for (int l = m + lane; l <= ell; l += 64) out[l] = make_double2(0.0, 0.0);
         return;
@@ -420,21 +456,39 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
     // part rp = lane >> 4; the four parts then combine across lanes 16 apart
     const int rb = lane & 15, rp = lane >> 4;
     const int rcol = (rb & 1) * 33 + rp * 8;
-    for (int l0 = L0; l0 <= ell; l0 += kLegB) {
-        if (l0 <= hi) inject<K>(l0, ls, s0, s1, p1, p2);
-        ana_block<K>(l0, A, x, p1, p2, gpr, gpi, gmr, gmi, red, lane);
-        wave_lds_sync();
-        double sr = 0.0, si = 0.0;
+    double (*cf)[kChunk] = coef[w];
+    // A_l for l = c + lane; ana_block runs whole blocks, so rows are read up
+    // to l_iter + 16 (inside the table padding) and zero beyond
+    auto fetch = [&](int c) {
+        const int l = c + lane;
+        return l <= ell + kLegB ? A[l] : 0.0;
+    };
+    double na = fetch(L0);
+    cf[0][lane] = na;
+    wave_lds_sync();
+    int cur = 0;
+    for (int cb = L0; cb <= ell; cb += kChunk) {
+        na = fetch(cb + kChunk);  // next chunk, in flight meanwhile
+        const int cend = min(cb + kChunk - 1, ell);
+        for (int l0 = cb; l0 <= cend; l0 += kLegB) {
+            if (l0 <= hi) inject<K>(l0, ls, s0, s1, p1, p2);
+            ana_block<K>(cf[cur], l0 - cb, x, p1, p2, gpr, gpi, gmr, gmi, red, lane);
+            wave_lds_sync();
+            double sr = 0.0, si = 0.0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const double2 v = red[rb >> 1][rcol + i];
-            sr += v.x;
-            si += v.y;
+            for (int i = 0; i < 8; ++i) {
+                const double2 v = red[rb >> 1][rcol + i];
+                sr += v.x;
+                si += v.y;
+            }
+            wave_lds_sync();
+            sr = xsum_rows(sr);
+            si = xsum_rows(si);
+            if (rp == 0 && l0 + rb <= ell) out[l0 + rb] = make_double2(sr, si);
         }
+        cf[cur ^ 1][lane] = na;
         wave_lds_sync();
-        sr = xsum_rows(sr);
-        si = xsum_rows(si);
-        if (rp == 0 && l0 + rb <= ell) out[l0 + rb] = make_double2(sr, si);
+        cur ^= 1;
     }
 }
 
@@ -477,8 +531,8 @@ dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const
                            hipStream_t s) {
     SynArgs a{p->d_x, p->d_ls, p->d_s0, p->d_s1, p->d_A, ap, spec, ell_dev, p->lmax, p->nq, p->lp};
     ProfScope ps(p, s, PROF_LEG_SYN);
-    hipLaunchKernelGGL(k_leg_syn<kSynK>, dim3(p->nchunk_syn, (p->lmax + kLegWaves) / kLegWaves),
-                       dim3(64 * kLegWaves), 0, s, a);
+    const int ng8 = ((p->lmax + kLegWaves) / kLegWaves + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_leg_syn<kSynK>, dim3(p->nchunk_syn * ng8), dim3(64 * kLegWaves), 0, s, a);
     DMWF_HIP(hipGetLastError());
     return DMWF_OK;
 }
@@ -488,8 +542,8 @@ dmwf_status launch_leg_ana(dmwf_plan* p, const double2* spec, double2* part, con
     AnaArgs a{p->d_x,  p->d_ls, p->d_s0, p->d_s1, p->d_A, spec, part,
               (size_t)p->nalm + kTablePad, ell_dev, p->lmax, p->nq, p->lp};
     ProfScope ps(p, s, PROF_LEG_ANA);
-    hipLaunchKernelGGL(k_leg_ana<kAnaK>, dim3(p->nchunk_ana, (p->lmax + kLegWaves) / kLegWaves),
-                       dim3(64 * kLegWaves), 0, s, a);
+    const int ng8 = ((p->lmax + kLegWaves) / kLegWaves + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_leg_ana<kAnaK>, dim3(p->nchunk_ana * ng8), dim3(64 * kLegWaves), 0, s, a);
     DMWF_HIP(hipGetLastError());
     return DMWF_OK;
 }
