@@ -362,7 +362,10 @@ constexpr int kRedRow = 66;
 // Pair j leaves through
 // red[j][.]: lanes 0..31 hold the even l0 + 2j summed over lanes i and i+32,
 // lanes 32..63 the odd l0 + 2j + 1.
-template <int K>
+// Slots t < T0 hold rings that have not started yet (all their starts lie
+// beyond this block): their terms are zero and their state stays (0, 0), so
+// they are skipped.
+template <int K, int T0>
 __device__ __forceinline__ void ana_block(const double* CA, int i0,
                                           const double (&x)[K], double (&p1)[K], double (&p2)[K],
                                           const double (&gpr)[K], const double (&gpi)[K],
@@ -374,7 +377,7 @@ __device__ __forceinline__ void ana_block(const double* CA, int i0,
         const double Ae = AA.x, Ao = AA.y;
         double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;
 #pragma unroll
-        for (int t = 0; t < K; ++t) {
+        for (int t = T0; t < K; ++t) {
             const double ue = fma(Ae * x[t], p1[t], -p2[t]);
             er = fma(ue, gpr[t], er);
             ei = fma(ue, gpi[t], ei);
@@ -386,6 +389,23 @@ __device__ __forceinline__ void ana_block(const double* CA, int i0,
         }
         red[j][lane + (lane >> 5)] = make_double2(xsum32(er, orr), xsum32(ei, oi));
     }
+}
+
+// ana_block over the slots t0..K-1, t0 wave-uniform.
+template <int K, int T = 0>
+__device__ __forceinline__ void ana_block_from(int t0, const double* CA, int i0,
+                                               const double (&x)[K], double (&p1)[K],
+                                               double (&p2)[K], const double (&gpr)[K],
+                                               const double (&gpi)[K], const double (&gmr)[K],
+                                               const double (&gmi)[K], double2 (*red)[kRedRow],
+                                               int lane) {
+    if constexpr (T < K - 1) {
+        if (t0 > T) {
+            ana_block_from<K, T + 1>(t0, CA, i0, x, p1, p2, gpr, gpi, gmr, gmi, red, lane);
+            return;
+        }
+    }
+    ana_block<K, T>(CA, i0, x, p1, p2, gpr, gpi, gmr, gmi, red, lane);
 }
 
 template <int K>
@@ -442,6 +462,9 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
     // loop bounds below live in scalar registers
     lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
     hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
+    int slot_lo[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) slot_lo[t] = __builtin_amdgcn_readfirstlane(wave_min(ls[t]));
     const long long base = alm_base(m, a.lmax);
     double2* out = a.part + tile.chunk * a.part_stride + base;
     if (lo > ell) {
@@ -472,7 +495,13 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
         const int cend = min(cb + kChunk - 1, ell);
         for (int l0 = cb; l0 <= cend; l0 += kLegB) {
             if (l0 <= hi) inject<K>(l0, ls, s0, s1, p1, p2);
-            ana_block<K>(cf[cur], l0 - cb, x, p1, p2, gpr, gpi, gmr, gmi, red, lane);
+            // first slot with a started ring (uniform); the slots are ordered
+            // from the pole towards the equator, where rings start earliest
+            int t0 = K;
+#pragma unroll
+            for (int t = K - 1; t >= 0; --t)
+                if (slot_lo[t] <= l0) t0 = t;
+            ana_block_from<K>(t0, cf[cur], l0 - cb, x, p1, p2, gpr, gpi, gmr, gmi, red, lane);
             wave_lds_sync();
             double sr = 0.0, si = 0.0;
 #pragma unroll
