@@ -27,6 +27,44 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 __global__ void k_set_int(int* p, int v) { *p = v; }
 
 // Largest l with C_l - mu > 0 (the Heaviside truncation of S_bar), or -1.
+// Level set-up of one iteration call in a single launch: every block finds
+// l_iter = max{l : C_l > mu} itself; block 0 stores it and sets the analysis
+// band of the ring stage to lmax; each thread then finds the m bound of one
+// ring pair (largest m <= l_iter whose suffix-minimum start is <= l_iter).
+__global__ void k_level(const double* __restrict__ cl, int lmax, double mu,
+                        const int* __restrict__ lsmin, int nq, int* ell_out, int* ell_ana_out,
+                        int* __restrict__ mhi) {
+    __shared__ int w[4];
+    int best = -1;
+    for (int l = threadIdx.x; l <= lmax; l += blockDim.x)
+        if (cl[l] - mu > 0.0) best = l;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o));
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = best;
+    __syncthreads();
+    int ell = w[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) ell = max(ell, w[i]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *ell_out = ell;
+        *ell_ana_out = lmax;
+    }
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const int* row = lsmin + (size_t)q * (lmax + 1);
+    int hi = min(ell, lmax);
+    if (hi < 0 || row[0] > ell) {
+        mhi[q] = -1;
+        return;
+    }
+    int lo = 0;  // row[lo] <= ell
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row[mid] <= ell) lo = mid;
+        else hi = mid - 1;
+    }
+    mhi[q] = lo;
+}
+
 __global__ void k_ell_from_cl(const double* __restrict__ cl, int lmax, double mu, int* out) {
     int best = -1;
     for (int l = threadIdx.x; l <= lmax; l += blockDim.x)
@@ -573,7 +611,8 @@ namespace {
 // step from the residual spectrum in the workspace, synthesis, pixel step.
 dmwf_status iterate_body(dmwf_plan* p, const Ws& W, double xi, double alpha, double mu,
                          const double* cl, const double* d, const double* w, double2* a,
-                         double* s_map, int first_pix, const int* mhi_ana, hipStream_t s) {
+                         double* s_map, int first_pix, const int* mhi_ana, double* cauchy_out,
+                         hipStream_t s) {
     dmwf_status st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), s);
     if (st != DMWF_OK) return st;
     {
@@ -597,7 +636,7 @@ dmwf_status iterate_body(dmwf_plan* p, const Ws& W, double xi, double alpha, dou
     if (st != DMWF_OK) return st;
     {
         ProfScope ps(p, s, PROF_REDUCE);
-        hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, s, W.cpart(), p->nq, W.out2());
+        hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, s, W.cpart(), p->nq, cauchy_out);
     }
     DMWF_HIP(hipGetLastError());
     return DMWF_OK;
@@ -668,15 +707,15 @@ dmwf_status dmwf_dm_iterate(dmwf_plan* p, double xi, double alpha, const double*
     hipStream_t s = static_cast<hipStream_t>(stream);
     const double mu = (xi - alpha) / (1.0 / p->omega);
     {
+        // l_iter, the m bounds at l_iter, and the analysis band of the ring
+        // stage set to lmax: the residual spectrum left for the next call
+        // covers every m, so a later call at a smaller xi (larger l_iter)
+        // finds it complete
         ProfScope ps(p, s, PROF_MISC);
-        hipLaunchKernelGGL(k_ell_from_cl, dim3(1), dim3(256), 0, s, cl, p->lmax, mu, W.ell());
-        // the residual spectrum left for the next call covers every m, so a
-        // later call at a smaller xi (larger l_iter) finds it complete
-        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell_ana(), p->lmax);
+        hipLaunchKernelGGL(k_level, dim3((p->nq + 255) / 256), dim3(256), 0, s, cl, p->lmax, mu,
+                           p->d_lsmin, p->nq, W.ell(), W.ell_ana(), W.mhi());
     }
     DMWF_HIP(hipGetLastError());
-    st = launch_mhi(p, W.ell(), W.mhi(), s);
-    if (st != DMWF_OK) return st;
     if (first) {
         RingIO io{};
         io.d = d;
@@ -685,11 +724,8 @@ dmwf_status dmwf_dm_iterate(dmwf_plan* p, double xi, double alpha, const double*
                          p->d_mhi_full, io, s);
         if (st != DMWF_OK) return st;
     }
-    st = iterate_body(p, W, xi, alpha, mu, cl, d, ninv, reinterpret_cast<double2*>(alm_state),
-                      s_map, first ? 1 : 0, p->d_mhi_full, s);
-    if (st != DMWF_OK) return st;
-    DMWF_HIP(hipMemcpyAsync(cauchy2, W.out2(), 2 * sizeof(double), hipMemcpyDeviceToDevice, s));
-    return DMWF_OK;
+    return iterate_body(p, W, xi, alpha, mu, cl, d, ninv, reinterpret_cast<double2*>(alm_state),
+                        s_map, first ? 1 : 0, p->d_mhi_full, cauchy2, s);
 }
 
 dmwf_status dmwf_wf_residual(dmwf_plan* p, const double* cl, const double* d, const double* ninv,
@@ -870,7 +906,8 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
             const double eps = xi <= alpha ? sc->eps_final : sc->eps_coarse;
             int it = 0;
             while (true) {
-                st = iterate_body(p, W, xi, alpha, mu, cl, d, w, a, smap, first_pix, W.mhi(), s);
+                st = iterate_body(p, W, xi, alpha, mu, cl, d, w, a, smap, first_pix, W.mhi(), W.out2(),
+                                  s);
                 if (st != DMWF_OK) return st;
                 first_pix = 0;
                 DMWF_HIP(hipMemcpyAsync(h2, W.out2(), sizeof(h2), hipMemcpyDeviceToHost, s));
