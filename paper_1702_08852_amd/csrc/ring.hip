@@ -311,6 +311,8 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     const int ella = min(*a.ell_ana, a.mhi_ana[q]);
     const int tid = threadIdx.x;
     double rn[J], rs[J];
+    // m per thread and batch in the fold and unfold
+    constexpr int FB = NT >= 512 ? 5 : 6;
 
     const bool syn = (a.mode == RING_SYN || a.mode == RING_ITER || a.mode == RING_SYN_WRES);
     if (syn) {
@@ -329,11 +331,13 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
             for (int k = tid; k < M; k += NT)
                 if (k >= n || (k > ell && k < n - ell)) buf[pad(k)] = make_double2(0.0, 0.0);
         }
-        for (int m0 = tid; m0 <= ell; m0 += 4 * NT) {
-            // loads for four m first (F row entries and the chirp at their bins)
-            double2 fnv[4], fsv[4], cpv[4], cmv[4];
+        for (int m0 = tid; m0 <= ell; m0 += FB * NT) {
+            // loads for FB m first (F row entries and the chirp at their bins):
+            // at lmax = 2 nside one batch covers the row, so the fold waits on
+            // memory once
+            double2 fnv[FB], fsv[FB], cpv[FB], cmv[FB];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < FB; ++u) {
                 const int m = m0 + u * NT;
                 fnv[u] = fsv[u] = cpv[u] = cmv[u] = make_double2(0.0, 0.0);
                 if (m <= ell) {
@@ -347,7 +351,7 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
                 }
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < FB; ++u) {
                 const int m = m0 + u * NT;
                 if (m > ell) continue;
                 double sn, cs;
@@ -442,7 +446,7 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
         // combined and stored, so the loads of one pixel never wait on the
         // store of another.
         double num = 0.0, den = 0.0;
-        constexpr int JH = J > 4 ? 4 : J;  // pixels per half, bounds register use
+        constexpr int JH = J;  // all of the thread's pixels in one batch of loads
 #pragma unroll
         for (int t0 = 0; t0 < J; t0 += JH) {
             double yN[JH], yS[JH], dN[JH], dS[JH], wN[JH], wS[JH], pN[JH], pS[JH];
@@ -520,10 +524,10 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
         }
     }
     // Z_k = DFT(z)_k; split the two real rings and unfold to m
-    for (int m0 = tid; m0 <= ella; m0 += 4 * NT) {
-        double2 ckv[4], ccv[4];
+    for (int m0 = tid; m0 <= ella; m0 += FB * NT) {
+        double2 ckv[FB], ccv[FB];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < FB; ++u) {
             const int m = m0 + u * NT;
             ckv[u] = ccv[u] = make_double2(1.0, 0.0);
             if (blue && m <= ella) {
@@ -533,7 +537,7 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < FB; ++u) {
             const int m = m0 + u * NT;
             if (m > ella) continue;
             const int k = m % n;
