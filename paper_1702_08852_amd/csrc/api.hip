@@ -97,11 +97,18 @@ __global__ void k_prep_syn(const double2* __restrict__ alm, const double* __rest
 //   b = Omega g_lm sum_chunks part,  a <- f_l (a + b),  a' = g_lm a,
 //   f_l = S_bar_l / (S_bar_l + xi/sigma),  S_bar_l = max(C_l - mu, 0).
 // Slots with l > l_iter are set to zero without reading the partial sums.
+// With ctrl (the solve loop) mu and xi / sigma are the current level's, and
+// nothing runs once the solve has stopped.
 __global__ void k_diag(double2* __restrict__ a, double2* __restrict__ ap,
                        const double2* __restrict__ part, int nchunk, size_t stride,
                        const double* __restrict__ g, const double* __restrict__ cl, double mu,
                        double xi_over_sigma, double omega, const int* __restrict__ ell_dev,
-                       int lmax) {
+                       int lmax, const DevCtrl* __restrict__ ctrl) {
+    if (ctrl) {
+        if (ctrl->done) return;
+        mu = ctrl->mu;
+        xi_over_sigma = ctrl->xi_over_sigma;
+    }
     const int m = blockIdx.y;
     const int l = m + blockIdx.x * blockDim.x + threadIdx.x;
     if (l > lmax) return;
@@ -143,6 +150,109 @@ __global__ void k_adj_final(const double2* __restrict__ part, int nchunk, size_t
     }
     const double sc = scale * g[i];
     out[i] = make_double2(sc * sr, m == 0 ? 0.0 : sc * si);
+}
+
+// m bound of ring pair q at the l_iter of every level: mhi_tab[k][q].
+__global__ void k_level_tab(const int* __restrict__ lsmin, int nq, int lmax,
+                            const DevLevel* __restrict__ levels, int nlev,
+                            int* __restrict__ mhi_tab) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= (long long)nlev * nq) return;
+    const int k = (int)(i / nq), q = (int)(i % nq);
+    const int ell = levels[k].ell;
+    const int* row = lsmin + (size_t)q * (lmax + 1);
+    int hi = min(ell, lmax);
+    if (hi < 0 || row[0] > ell) {
+        mhi_tab[i] = -1;
+        return;
+    }
+    int lo = 0;  // row[lo] <= ell
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row[mid] <= ell) lo = mid;
+        else hi = mid - 1;
+    }
+    mhi_tab[i] = lo;
+}
+
+__device__ void ctrl_enter_level(DevCtrl* c, const DevLevel* levels, int k, int* ell_out,
+                                 int* ell_ana_out) {
+    c->level = k;
+    c->it_level = 0;
+    c->xi = levels[k].xi;
+    c->mu = levels[k].mu;
+    c->xi_over_sigma = levels[k].xi_over_sigma;
+    *ell_out = levels[k].ell;
+    *ell_ana_out = levels[k].ell_next;
+}
+
+__global__ void k_ctrl_init(DevCtrl* c, const DevLevel* levels, int nlev, int max_iter,
+                            int replay, int* ell_out, int* ell_ana_out, int* lev_iters) {
+    c->done = 0;
+    c->status = 0;
+    c->total = 0;
+    c->nlev = nlev;
+    c->max_iter = max_iter;
+    c->replay = replay;
+    c->ratio = 0.0;
+    for (int k = 0; k < nlev; ++k) lev_iters[k] = 0;
+    ctrl_enter_level(c, levels, 0, ell_out, ell_ana_out);
+}
+
+// After each iteration of the solve loop (one block): the Cauchy sums over
+// the ring pairs in a fixed order, the ratio ||s_i - s_{i-1}|| / ||s_i||, and
+// the schedule's decision: stay on the level, move to the next one (a
+// level's tolerance met, or its replayed count reached), or stop (the last
+// level met its tolerance, the iteration cap, or a NaN ratio).
+__global__ void k_control(const double* __restrict__ cpart, int n, DevCtrl* c,
+                          const DevLevel* __restrict__ levels, int* lev_iters, int* ell_out,
+                          int* ell_ana_out, double* out2) {
+    __shared__ double sa[256], sb[256];
+    if (c->done) return;
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        a += cpart[2 * i];
+        b += cpart[2 * i + 1];
+    }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            sa[threadIdx.x] += sa[threadIdx.x + st];
+            sb[threadIdx.x] += sb[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double num = sa[0], den = sb[0];
+    out2[0] = num;
+    out2[1] = den;
+    const double ratio = den > 0.0 ? sqrt(num / den) : (num == 0.0 ? 0.0 : INFINITY);
+    c->ratio = ratio;
+    c->it_level += 1;
+    c->total += 1;
+    const int k = c->level;
+    lev_iters[k] = c->it_level;
+    if (isnan(ratio)) {
+        c->status = 2;
+        c->done = 1;
+        return;
+    }
+    const bool advance = c->replay ? c->it_level >= levels[k].replay : ratio < levels[k].eps;
+    if (advance) {
+        if (k + 1 >= c->nlev) {
+            c->status = 0;
+            c->done = 1;
+        } else {
+            ctrl_enter_level(c, levels, k + 1, ell_out, ell_ana_out);
+        }
+        return;
+    }
+    if (c->total >= c->max_iter) {
+        c->status = 1;
+        c->done = 1;
+    }
 }
 
 __global__ void k_zero2(double2* p, long long n) {
@@ -270,6 +380,10 @@ struct Ws {
     int* ell_ana() const { return reinterpret_cast<int*>(base + off.scal + 8); }
     double* out2() const { return reinterpret_cast<double*>(base + off.scal + 16); }
     double* scal_d() const { return reinterpret_cast<double*>(base + off.scal + 64); }
+    DevCtrl* ctrl() const { return reinterpret_cast<DevCtrl*>(base + off.ctrl); }
+    DevLevel* levels() const { return reinterpret_cast<DevLevel*>(base + off.levels); }
+    int* lev_iters() const { return reinterpret_cast<int*>(base + off.lev_iters); }
+    int* mhi_tab() const { return reinterpret_cast<int*>(base + off.mhi_tab); }
     WsLayout off;
 };
 
@@ -324,6 +438,9 @@ void dmwf_plan_destroy(dmwf_plan* p) {
         (void)hipEventDestroy(e.stop);
     }
     free_ring_tables(p);
+    if (p->h_ctrl) (void)hipHostFree(p->h_ctrl);
+    for (hipEvent_t e : p->batch_ev)
+        if (e) (void)hipEventDestroy(e);
     void* bufs[] = {p->d_x, p->d_sint, p->d_nph, p->d_phi0pi, p->d_start_n, p->d_start_s,
                     p->d_A, p->d_g,    p->d_ls,  p->d_s0,     p->d_s1, p->d_lsmin,
                     p->d_mhi_full};
@@ -488,7 +605,21 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
     off = align256(off + (size_t)nq * sizeof(int));
     w.scal = off;
     off = align256(off + scal_bytes(p));
+    w.ctrl = off;
+    off = align256(off + sizeof(DevCtrl));
+    w.levels = off;
+    off = align256(off + kMaxLevels * sizeof(DevLevel));
+    w.lev_iters = off;
+    off = align256(off + kMaxLevels * sizeof(int));
+    w.mhi_tab = off;
+    off = align256(off + (size_t)kMaxLevels * nq * sizeof(int));
     w.total = off;
+    if (hipHostMalloc((void**)&p->h_ctrl, 2 * sizeof(DevCtrl), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&p->batch_ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->batch_ev[1], hipEventDisableTiming) != hipSuccess) {
+        set_error("allocation of the solve-loop host buffer failed");
+        return fail(DMWF_ERR_OOM);
+    }
     *out = p;
     return DMWF_OK;
 }
@@ -556,7 +687,7 @@ dmwf_status dmwf_alm2map(dmwf_plan* p, const double* alm, double* map, void* ws,
                                W.ap(), p->lmax);
         }
         DMWF_HIP(hipGetLastError());
-        st = launch_leg_syn(p, W.ap(), W.spec(), W.ell(), s);
+        st = launch_leg_syn(p, W.ap(), W.spec(), W.ell(), nullptr, s);
         if (st != DMWF_OK) return st;
         RingIO io{};
         io.map_out = mp;
@@ -589,7 +720,7 @@ dmwf_status dmwf_adjoint(dmwf_plan* p, const double* map, double* alm, int scale
         st = launch_ring(p, RING_ANA, W.spec(), W.ell(), W.ell(), p->d_mhi_full, p->d_mhi_full, io,
                          s);
         if (st != DMWF_OK) return st;
-        st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), s);
+        st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), nullptr, s);
         if (st != DMWF_OK) return st;
         {
             ProfScope ps(p, s, PROF_DIAG);
@@ -609,20 +740,26 @@ namespace {
 
 // The iteration body shared by dmwf_dm_iterate and the solve loop: harmonic
 // step from the residual spectrum in the workspace, synthesis, pixel step.
+// With ctrl (the solve loop) the level parameters come from the device
+// control block and the iteration ends with the level decision; without it
+// (dmwf_dm_iterate) they are the host values and the Cauchy sums go to
+// cauchy_out.
 dmwf_status iterate_body(dmwf_plan* p, const Ws& W, double xi, double alpha, double mu,
                          const double* cl, const double* d, const double* w, double2* a,
                          double* s_map, int first_pix, const int* mhi_ana, double* cauchy_out,
-                         hipStream_t s) {
-    dmwf_status st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), s);
+                         DevCtrl* ctrl, hipStream_t s) {
+    const int* done = ctrl ? &ctrl->done : nullptr;
+    dmwf_status st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), done, s);
     if (st != DMWF_OK) return st;
     {
         ProfScope ps(p, s, PROF_DIAG);
         hipLaunchKernelGGL(k_diag, alm_grid(p->lmax, 256), dim3(256), 0, s, a, W.ap(), W.part(),
                            p->nchunk_ana, (size_t)p->nalm + kTablePad, p->d_g, cl, mu,
-                           xi * p->omega, p->omega, W.ell(), p->lmax);
+                           xi * p->omega, p->omega, W.ell(), p->lmax,
+                           static_cast<const DevCtrl*>(ctrl));
     }
     DMWF_HIP(hipGetLastError());
-    st = launch_leg_syn(p, W.ap(), W.spec(), W.ell(), s);
+    st = launch_leg_syn(p, W.ap(), W.spec(), W.ell(), done, s);
     if (st != DMWF_OK) return st;
     RingIO io{};
     io.d = d;
@@ -632,11 +769,18 @@ dmwf_status iterate_body(dmwf_plan* p, const Ws& W, double xi, double alpha, dou
     io.xi = xi;
     io.alpha = alpha;
     io.first = first_pix;
+    io.ctrl = ctrl;
+    io.mhi_tab = W.mhi_tab();
     st = launch_ring(p, RING_ITER, W.spec(), W.ell(), W.ell_ana(), W.mhi(), mhi_ana, io, s);
     if (st != DMWF_OK) return st;
     {
         ProfScope ps(p, s, PROF_REDUCE);
-        hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, s, W.cpart(), p->nq, cauchy_out);
+        if (ctrl)
+            hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, s, W.cpart(), p->nq, ctrl,
+                               W.levels(), W.lev_iters(), W.ell(), W.ell_ana(), W.out2());
+        else
+            hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, s, W.cpart(), p->nq,
+                               cauchy_out);
     }
     DMWF_HIP(hipGetLastError());
     return DMWF_OK;
@@ -652,7 +796,7 @@ dmwf_status residual_map(dmwf_plan* p, const Ws& W, const double* cl, const doub
                            p->lmax);
     }
     DMWF_HIP(hipGetLastError());
-    dmwf_status st = launch_leg_syn(p, W.ap(), W.spec(), W.ell(), s);
+    dmwf_status st = launch_leg_syn(p, W.ap(), W.spec(), W.ell(), nullptr, s);
     if (st != DMWF_OK) return st;
     RingIO io{};
     io.d = d;
@@ -660,7 +804,7 @@ dmwf_status residual_map(dmwf_plan* p, const Ws& W, const double* cl, const doub
     st = launch_ring(p, RING_SYN_WRES, W.spec(), W.ell(), W.ell(), p->d_mhi_full, p->d_mhi_full, io,
                      s);
     if (st != DMWF_OK) return st;
-    st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), s);
+    st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), nullptr, s);
     if (st != DMWF_OK) return st;
     const size_t stride = (size_t)p->nalm + kTablePad;
     hipLaunchKernelGGL(k_adj_final, alm_grid(p->lmax, 256), dim3(256), 0, s, W.part(),
@@ -668,7 +812,7 @@ dmwf_status residual_map(dmwf_plan* p, const Ws& W, const double* cl, const doub
     st = launch_ring(p, RING_ANA_WD, W.spec(), W.ell(), W.ell(), p->d_mhi_full, p->d_mhi_full, io,
                      s);
     if (st != DMWF_OK) return st;
-    st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), s);
+    st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), nullptr, s);
     if (st != DMWF_OK) return st;
     hipLaunchKernelGGL(k_adj_final, alm_grid(p->lmax, 256), dim3(256), 0, s, W.part(),
                        p->nchunk_ana, stride, p->d_g, W.aux(), 1.0, p->lmax);
@@ -725,7 +869,7 @@ dmwf_status dmwf_dm_iterate(dmwf_plan* p, double xi, double alpha, const double*
         if (st != DMWF_OK) return st;
     }
     return iterate_body(p, W, xi, alpha, mu, cl, d, ninv, reinterpret_cast<double2*>(alm_state),
-                        s_map, first ? 1 : 0, p->d_mhi_full, cauchy2, s);
+                        s_map, first ? 1 : 0, p->d_mhi_full, cauchy2, nullptr, s);
 }
 
 dmwf_status dmwf_wf_residual(dmwf_plan* p, const double* cl, const double* d, const double* ninv,
@@ -834,7 +978,7 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
                 hipLaunchKernelGGL(k_prep_syn, alm_grid(L, 256), dim3(256), 0, s, a, p->d_g,
                                    W.ap(), L);
             }
-            st = launch_leg_syn(p, W.ap(), W.spec(), W.ell(), s);
+            st = launch_leg_syn(p, W.ap(), W.spec(), W.ell(), nullptr, s);
             if (st != DMWF_OK) return st;
             RingIO io{};
             io.map_out = smap;
@@ -866,75 +1010,82 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
         }
         DMWF_HIP(hipGetLastError());
 
-        int total = 0, nlev = 0, ell_prev = L;
-        double ratio = 0.0;
-        bool capped = false;
-        double h2[2];
-        for (size_t lev = 0; lev < xis.size() && !capped; ++lev) {
-            const double xi = xis[lev];
-            const double mu = (xi - alpha) / sigma;
+        // a1 / a6 on the device: the level table goes to the workspace, and
+        // after every iteration k_control takes the schedule's decision.  The
+        // host enqueues iterations in growing batches with two batches in
+        // flight and reads the control block once per batch, so the GPU never
+        // waits for the host; iterations enqueued after the stop do nothing.
+        const int nl = (int)xis.size();
+        if (nl > kMaxLevels) {
+            set_error("the schedule has " + std::to_string(nl) + " levels, more than " +
+                      std::to_string(kMaxLevels));
+            return DMWF_ERR_INVALID_ARG;
+        }
+        std::vector<DevLevel> lv(nl);
+        for (int k = 0; k < nl; ++k) {
+            const double xi = xis[k], mu = (xi - alpha) / sigma;
             int ell = -1;
             for (int l = 0; l <= L; ++l)
                 if (hcl[l] - mu > 0.0) ell = l;
-            if (lev > 0 && ell > ell_prev) {
-                // The residual r = c(xi_prev) (d - s) carried into this level was
-                // analysed only for m <= l_iter of the previous level; redo it
-                // for every m this level uses.
-                {
-                    ProfScope ps(p, s, PROF_MISC);
-                    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell(), ell);
-                }
-                st = launch_mhi(p, W.ell(), W.mhi(), s);
-                if (st != DMWF_OK) return st;
-                RingIO io{};
-                io.map_in = smap;
-                io.d = d;
-                io.w = w;
-                io.xi = xis[lev - 1];
-                io.alpha = alpha;
-                st = launch_ring(p, RING_ANA_CRES, W.spec(), W.ell(), W.ell(), W.mhi(), W.mhi(), io, s);
-                if (st != DMWF_OK) return st;
-            }
-            {
-                ProfScope ps(p, s, PROF_MISC);
-                hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell(), ell);
-                hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell_ana(), ell);
-            }
-            st = launch_mhi(p, W.ell(), W.mhi(), s);
-            if (st != DMWF_OK) return st;
-            ell_prev = ell;
-            const double eps = xi <= alpha ? sc->eps_final : sc->eps_coarse;
-            int it = 0;
-            while (true) {
-                st = iterate_body(p, W, xi, alpha, mu, cl, d, w, a, smap, first_pix, W.mhi(), W.out2(),
-                                  s);
-                if (st != DMWF_OK) return st;
+            lv[k] = DevLevel{xi,  mu, xi * p->omega, xi <= alpha ? sc->eps_final : sc->eps_coarse,
+                             ell, 0,  sc->replay_iters ? sc->replay_iters[k] : 0, 0};
+        }
+        for (int k = 0; k < nl; ++k) lv[k].ell_next = lv[std::min(k + 1, nl - 1)].ell;
+        DMWF_HIP(hipMemcpyAsync(W.levels(), lv.data(), nl * sizeof(DevLevel), hipMemcpyHostToDevice,
+                                s));
+        {
+            ProfScope ps(p, s, PROF_MISC);
+            const long long nt = (long long)nl * p->nq;
+            hipLaunchKernelGGL(k_level_tab, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s,
+                               p->d_lsmin, p->nq, L, W.levels(), nl, W.mhi_tab());
+            hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(1), 0, s, W.ctrl(), W.levels(), nl,
+                               sc->max_iter, sc->replay_iters ? 1 : 0, W.ell(), W.ell_ana(),
+                               W.lev_iters());
+        }
+        DMWF_HIP(hipGetLastError());
+        auto enqueue = [&](int nit, int slot) -> dmwf_status {
+            for (int i = 0; i < nit; ++i) {
+                dmwf_status e = iterate_body(p, W, alpha, alpha, 0.0, cl, d, w, a, smap, first_pix,
+                                             W.mhi(), W.out2(), W.ctrl(), s);
+                if (e != DMWF_OK) return e;
                 first_pix = 0;
-                DMWF_HIP(hipMemcpyAsync(h2, W.out2(), sizeof(h2), hipMemcpyDeviceToHost, s));
-                DMWF_HIP(hipStreamSynchronize(s));
-                ++it;
-                ++total;
-                ratio = h2[1] > 0.0 ? std::sqrt(h2[0] / h2[1]) : (h2[0] == 0.0 ? 0.0 : INFINITY);
-                if (std::isnan(ratio)) {
-                    set_error("Cauchy ratio is NaN");
-                    return DMWF_ERR_NONFINITE;
-                }
-                if (sc->replay_iters) {
-                    if (it >= sc->replay_iters[lev]) break;
-                } else if (ratio < eps) {
-                    break;
-                }
-                if (total >= sc->max_iter) {
-                    capped = true;
-                    break;
-                }
             }
-            if (stats && (int)lev < stats->cap_levels) {
-                if (stats->iters_per_level) stats->iters_per_level[lev] = it;
-                if (stats->xi_per_level) stats->xi_per_level[lev] = xi;
-                if (stats->lmax_per_level) stats->lmax_per_level[lev] = ell;
+            DMWF_HIP(hipMemcpyAsync(&p->h_ctrl[slot], W.ctrl(), sizeof(DevCtrl),
+                                    hipMemcpyDeviceToHost, s));
+            DMWF_HIP(hipEventRecord(p->batch_ev[slot], s));
+            return DMWF_OK;
+        };
+        int batch = 4, cur = 0;
+        st = enqueue(batch, cur);
+        if (st != DMWF_OK) return st;
+        DevCtrl fin{};
+        while (true) {
+            batch = std::min(2 * batch, 64);
+            st = enqueue(batch, cur ^ 1);
+            if (st != DMWF_OK) return st;
+            DMWF_HIP(hipEventSynchronize(p->batch_ev[cur]));
+            if (p->h_ctrl[cur].done) {
+                DMWF_HIP(hipEventSynchronize(p->batch_ev[cur ^ 1]));
+                fin = p->h_ctrl[cur ^ 1];
+                break;
             }
-            ++nlev;
+            cur ^= 1;
+        }
+        std::vector<int> its(nl, 0);
+        DMWF_HIP(hipMemcpy(its.data(), W.lev_iters(), nl * sizeof(int), hipMemcpyDeviceToHost));
+        if (fin.status == 2) {
+            set_error("Cauchy ratio is NaN");
+            return DMWF_ERR_NONFINITE;
+        }
+        const int nlev = fin.level + 1, total = fin.total;
+        const double ratio = fin.ratio;
+        const bool capped = fin.status == 1;
+        if (stats) {
+            for (int k = 0; k < nlev && k < stats->cap_levels; ++k) {
+                if (stats->iters_per_level) stats->iters_per_level[k] = its[k];
+                if (stats->xi_per_level) stats->xi_per_level[k] = lv[k].xi;
+                if (stats->lmax_per_level) stats->lmax_per_level[k] = lv[k].ell;
+            }
         }
         if (stats) {
             stats->n_levels = nlev;

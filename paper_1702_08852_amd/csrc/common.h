@@ -68,6 +68,26 @@ struct RingGeom {
     const long long* start_s; // first pixel of the south ring, -1 for the equator
 };
 
+// Device-side control of the solve loop.  The host enqueues iterations in
+// batches; after each iteration a one-block kernel sums the Cauchy partials,
+// takes the level decision of the cooling schedule and, once the solve has
+// stopped, sets `done`, after which every iteration kernel returns at once.
+struct DevLevel {
+    double xi, mu, xi_over_sigma, eps;
+    int ell, ell_next;  // l_iter of this level and of the next (the last: its own)
+    int replay;         // iterations to run on this level when replaying, else 0
+    int pad;
+};
+struct DevCtrl {
+    int done;    // nonzero: the solve has stopped
+    int status;  // 0 converged, 1 iteration cap reached, 2 NaN Cauchy ratio
+    int level, it_level, total, nlev, max_iter, replay;
+    double xi, mu, xi_over_sigma, ratio;
+};
+// Most cooling levels one solve may have (the per-level m-bound table is
+// kMaxLevels x ring pairs ints of workspace).
+constexpr int kMaxLevels = 1024;
+
 // Workspace layout (byte offsets from the workspace base).
 struct WsLayout {
     size_t spec;    // complex [nq][lp][2]: ring Fourier coefficients F_m / G_m, ring-major
@@ -77,6 +97,10 @@ struct WsLayout {
     size_t cpart;   // double  [nq][2]: Cauchy partial sums per ring pair
     size_t mhi;     // int     [nq]: per ring pair, the largest m carried at the current l_iter
     size_t scal;    // small scalars: ints and doubles
+    size_t ctrl;    // DevCtrl
+    size_t levels;  // DevLevel [kMaxLevels]
+    size_t lev_iters;  // int [kMaxLevels]: iterations run per level
+    size_t mhi_tab;    // int [kMaxLevels][nq]: m bound of every ring pair per level
     size_t total;
 };
 
@@ -118,6 +142,10 @@ struct dmwf_plan {
     hipEvent_t ring_fork = nullptr;
     hipEvent_t ring_join[3] = {nullptr, nullptr, nullptr};
     dmwf::WsLayout ws;
+    // pinned host copy of the control block, read after each batch of the
+    // solve loop (two batches in flight)
+    dmwf::DevCtrl* h_ctrl = nullptr;
+    hipEvent_t batch_ev[2] = {nullptr, nullptr};
     // profiling
     bool prof = false;
     std::vector<dmwf::ProfEvent> events;
@@ -180,10 +208,11 @@ __host__ __device__ inline long long alm_base(int m, int lmax) {
 
 // ---- launchers (ring.hip, legendre.hip, api.hip) ----
 dmwf_status launch_seeds(dmwf_plan* p, hipStream_t s);
+// done (may be NULL): device flag; the kernels return at once when it is set.
 dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const int* ell_dev,
-                           hipStream_t s);
+                           const int* done, hipStream_t s);
 dmwf_status launch_leg_ana(dmwf_plan* p, const double2* spec, double2* part, const int* ell_dev,
-                           hipStream_t s);
+                           const int* done, hipStream_t s);
 
 // Ring stage modes.  SYN: F -> map.  ANA*: a pixel map -> G, the map being
 // map_in (ANA), d on unmasked pixels (ANA_FIRST), w (d - map_in) (ANA_RESID),
@@ -209,6 +238,10 @@ struct RingIO {
     double* cpart;          // RING_ITER: Cauchy partials [nq][2]
     double xi, alpha;       // RING_ITER: pixel step coefficients
     int first;              // RING_ITER: s_prev taken as 0
+    // RING_ITER inside the solve loop: xi and the m bounds of the current and
+    // next level come from the device control block; nothing runs once done
+    const DevCtrl* ctrl;
+    const int* mhi_tab;
 };
 // ell_syn bounds the m of F used by the synthesis, ell_ana the m of G written
 // by the analysis (device scalars); mhi_syn / mhi_ana are the per-ring-pair

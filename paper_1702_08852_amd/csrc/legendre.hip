@@ -180,6 +180,7 @@ struct SynArgs {
     double2* spec;
     const int* ell;
     int lmax, nq, lp;
+    const int* done;
 };
 
 // The analysis takes its coefficient row through LDS, kChunk l at a time per
@@ -242,6 +243,7 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn(SynArgs a) {
     // results meet in LDS and leave as whole segments of the ring-major rows
     // of F.
     __shared__ double2 stage[K][64][kLegWaves][2];
+    if (a.done && *a.done) return;
     const int w = threadIdx.x >> 6;
     // wave-uniform; readfirstlane lets the compiler use scalar loads for the
     // per-(l, m) coefficients
@@ -331,6 +333,7 @@ struct AnaArgs {
     size_t part_stride;
     const int* ell;
     int lmax, nq, lp;
+    const int* done;
 };
 
 // Cross-lane sums through the lane-swap instructions (no LDS).  xsum32(a, b):
@@ -412,6 +415,7 @@ template <int K>
 __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
     __shared__ double2 red_all[kLegWaves][kLegB / 2][kRedRow];
     __shared__ double coef[kLegWaves][2][kChunk];  // per wave: two chunks of A
+    if (a.done && *a.done) return;
     const int w = threadIdx.x >> 6;
     const LegTile tile = leg_tile((a.nq + 64 * K - 1) / (64 * K));
     const int m = __builtin_amdgcn_readfirstlane(tile.group * kLegWaves + w);
@@ -557,8 +561,9 @@ dmwf_status launch_mhi(dmwf_plan* p, const int* ell_dev, int* mhi, hipStream_t s
 }
 
 dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const int* ell_dev,
-                           hipStream_t s) {
-    SynArgs a{p->d_x, p->d_ls, p->d_s0, p->d_s1, p->d_A, ap, spec, ell_dev, p->lmax, p->nq, p->lp};
+                           const int* done, hipStream_t s) {
+    SynArgs a{p->d_x, p->d_ls, p->d_s0, p->d_s1, p->d_A,  ap,
+              spec,   ell_dev, p->lmax, p->nq,   p->lp,   done};
     ProfScope ps(p, s, PROF_LEG_SYN);
     const int ng8 = ((p->lmax + kLegWaves) / kLegWaves + 7) / 8 * 8;
     hipLaunchKernelGGL(k_leg_syn<kSynK>, dim3(p->nchunk_syn * ng8), dim3(64 * kLegWaves), 0, s, a);
@@ -567,9 +572,9 @@ dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const
 }
 
 dmwf_status launch_leg_ana(dmwf_plan* p, const double2* spec, double2* part, const int* ell_dev,
-                           hipStream_t s) {
+                           const int* done, hipStream_t s) {
     AnaArgs a{p->d_x,  p->d_ls, p->d_s0, p->d_s1, p->d_A, spec, part,
-              (size_t)p->nalm + kTablePad, ell_dev, p->lmax, p->nq, p->lp};
+              (size_t)p->nalm + kTablePad, ell_dev, p->lmax, p->nq, p->lp, done};
     ProfScope ps(p, s, PROF_LEG_ANA);
     const int ng8 = ((p->lmax + kLegWaves) / kLegWaves + 7) / 8 * 8;
     hipLaunchKernelGGL(k_leg_ana<kAnaK>, dim3(p->nchunk_ana * ng8), dim3(64 * kLegWaves), 0, s, a);

@@ -297,6 +297,8 @@ template <int NT, int J, int MFIX>
 __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     extern __shared__ double2 buf[];
     __shared__ double2 red[NT / 64];
+    const DevCtrl* ctrl = a.io.ctrl;
+    if (ctrl && ctrl->done) return;
     const int q = a.qlist[blockIdx.x];
     const int n = a.g.nph[q];
     const int M = a.Mq[q];
@@ -307,8 +309,18 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     const double c = a.g.phi0pi[q];
     const bool eq = (q == a.nq - 1);
     const long long st0 = a.g.start_n[q], st1 = a.g.start_s[q];
-    const int ell = min(*a.ell_syn, a.mhi_syn[q]);
-    const int ella = min(*a.ell_ana, a.mhi_ana[q]);
+    int msyn, mana;
+    if (ctrl) {
+        // m bounds of the current level (synthesis) and of the next (analysis)
+        const int lev = ctrl->level, nxt = min(lev + 1, ctrl->nlev - 1);
+        msyn = a.io.mhi_tab[(size_t)lev * a.nq + q];
+        mana = a.io.mhi_tab[(size_t)nxt * a.nq + q];
+    } else {
+        msyn = a.mhi_syn[q];
+        mana = a.mhi_ana[q];
+    }
+    const int ell = min(*a.ell_syn, msyn);
+    const int ella = min(*a.ell_ana, mana);
     const int tid = threadIdx.x;
     double rn[J], rs[J];
     // m per thread and batch in the fold and unfold
@@ -486,7 +498,7 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
                     rn[t] = wN[u] * (dN[u] - yN[u]);
                     rs[t] = eq ? 0.0 : wS[u] * (dS[u] - yS[u]);
                 } else {
-                    const double xi = a.io.xi, xa = a.io.xi - a.io.alpha;
+                    const double xi = ctrl ? ctrl->xi : a.io.xi, xa = xi - a.io.alpha;
                     double ds = yN[u] - pN[u];
                     num = fma(ds, ds, num);
                     den = fma(yN[u], yN[u], den);
