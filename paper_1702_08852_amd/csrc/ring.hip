@@ -65,6 +65,16 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
 
+// Workgroup barrier that orders LDS only.  Global stores issued before it may
+// still be in flight: no thread of a workgroup reads global memory that
+// another thread of the same workgroup wrote (the F row of a ring pair is
+// read, and waited for, long before its G row is written over it).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // LDS layout: logical element e lives at e + e/16 (one pad slot per 16) so
 // that sixteen lanes touching sixteen consecutive butterflies' outputs of the
 // first pass fall in distinct banks.
@@ -169,7 +179,7 @@ __device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int M, 
             dft_small<R>(v[i]);
         }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
         const int j = tid + i * nt;
@@ -180,7 +190,7 @@ __device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int M, 
             for (int t = 0; t < R; ++t) buf[pad(o + t * Ns)] = v[i][t];
         }
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 // Forward DFT of length M = 2^logM in place, natural order in and out:
@@ -266,7 +276,7 @@ __device__ __forceinline__ double2 block_sum2(double u, double v, double2* scrat
     }
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0) scratch[w] = make_double2(u, v);
-    __syncthreads();
+    lds_barrier();
     double2 t = make_double2(0.0, 0.0);
     if (threadIdx.x == 0) {
 #pragma unroll
@@ -338,7 +348,7 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
         const bool alias = 2 * ell > n;
         if (alias) {
             for (int k = tid; k < M; k += NT) buf[pad(k)] = make_double2(0.0, 0.0);
-            __syncthreads();
+            lds_barrier();
         } else {
             for (int k = tid; k < M; k += NT)
                 if (k >= n || (k > ell && k < n - ell)) buf[pad(k)] = make_double2(0.0, 0.0);
@@ -401,14 +411,14 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         if (alias) {
             for (int k = tid; k < n; k += NT) {
                 double2 v = conj2(buf[pad(k)]);
                 if (blue) v = cmul(v, conj2(ch[k]));
                 buf[pad(k)] = v;
             }
-            __syncthreads();
+            lds_barrier();
         }
     } else {
         // analysis only: the input comes from the pixels
@@ -439,7 +449,7 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
         }
         ana_input<NT, J>(buf, rn, rs, n, M, blue, ch, tid);
     }
-    __syncthreads();
+    lds_barrier();
 
     // Each DFT is one FFT, or two around the filter product for Bluestein
     // rings, written as a loop so that the FFT code appears once per direction
@@ -450,7 +460,7 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
             fft<NT, MFIX>(buf, M, logM, tid);
             if (blue && step == 0) {
                 filter_product<NT>(buf, M, B, tid);
-                __syncthreads();
+                lds_barrier();
             }
         }
         // y_j = IDFT(Z)_j: blue: c_j buf_j; else conj(buf_j).  s^N = Re y, s^S = Im y.
@@ -523,16 +533,16 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
             }
         }
         if (a.mode == RING_SYN) return;
-        __syncthreads();
+        lds_barrier();
         ana_input<NT, J>(buf, rn, rs, n, M, blue, ch, tid);
-        __syncthreads();
+        lds_barrier();
     }
 #pragma unroll 1
     for (int step = 0; step < (blue ? 2 : 1); ++step) {
         fft<NT, MFIX>(buf, M, logM, tid);
         if (blue && step == 0) {
             filter_product<NT>(buf, M, B, tid);
-            __syncthreads();
+            lds_barrier();
         }
     }
     // Z_k = DFT(z)_k; split the two real rings and unfold to m
@@ -599,7 +609,7 @@ __global__ __launch_bounds__(NT) void k_chirp_spectrum(const int* __restrict__ q
         else if (M - t < n) v = ch[M - t];
         buf[pad(t)] = v;
     }
-    __syncthreads();
+    lds_barrier();
     fft<NT, 0>(buf, M, logM, threadIdx.x);
     for (int k = threadIdx.x; k < M; k += NT) bspec[boff[q] + k] = buf[pad(k)];
 }
