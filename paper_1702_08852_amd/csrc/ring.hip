@@ -146,7 +146,7 @@ __device__ __forceinline__ void dft_small(double2 (&v)[R]) {
 // which makes the pass safe in place; requires M / R <= BPT nt.
 template <int R, int BPT>
 __device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int M, int Ns, int tid,
-                                              int nt) {
+                                              int nt, const double2* __restrict__ tw) {
     const int nb = M / R;
     const int stride = M / R;
     double2 v[BPT][R];
@@ -158,12 +158,12 @@ __device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int M, 
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i][r] = buf[pad(j + r * stride)];
             if (Ns > 1) {
-                // w^r, w = e^{-2 pi i k / (Ns R)}: one sincospi and a product
-                // tree of depth at most four (a few ulps), no table loads
-                double sn, cs;
-                sincospi(-2.0 * k / (Ns * R), &sn, &cs);
+                // w^r, w = e^{-2 pi i k / (Ns R)} = omega_M^t: the base from the
+                // two-level root table, powers by a product tree of depth at
+                // most four (a few ulps)
+                const int t = k * (M / (Ns * R));
                 double2 wp[4];  // w^1, w^2, w^4, w^8
-                wp[0] = make_double2(cs, sn);
+                wp[0] = cmul(tw[t & 63], tw[64 + (t >> 6)]);
 #pragma unroll
                 for (int b = 1; b < 4; ++b) wp[b] = cmul(wp[b - 1], wp[b - 1]);
 #pragma unroll
@@ -199,7 +199,8 @@ __device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int M, 
 // class), MFIX = 0 takes it at run time.  Radix-16 passes keep one butterfly
 // per thread, which needs M / 16 <= NT.
 template <int NT, int MFIX>
-__device__ __forceinline__ void fft(double2* buf, int M, int logM, int tid) {
+__device__ __forceinline__ void fft(double2* buf, int M, int logM, int tid,
+                                    const double2* __restrict__ tw) {
     static_assert(MFIX == 0 || MFIX / 16 <= NT, "one radix-16 butterfly per thread");
     // opaque copy of the thread index: keeps the passes' LDS addresses from
     // being hoisted out of the caller's loop into long-lived registers
@@ -208,35 +209,48 @@ __device__ __forceinline__ void fft(double2* buf, int M, int logM, int tid) {
     int Ns = 1;
 #pragma unroll 1
     for (int p = 0; p < (lm >> 2); ++p) {
-        stockham_pass<16, 1>(buf, M, Ns, tid, NT);
+        stockham_pass<16, 1>(buf, M, Ns, tid, NT, tw);
         Ns <<= 4;
     }
     if constexpr (MFIX > 0) {
         constexpr int L = ilog2(MFIX) & 3;
         constexpr int NB = MFIX >> L;
         constexpr int BPT = NB > NT ? NB / NT : 1;
-        if constexpr (L == 3) stockham_pass<8, BPT>(buf, M, Ns, tid, NT);
-        else if constexpr (L == 2) stockham_pass<4, BPT>(buf, M, Ns, tid, NT);
-        else if constexpr (L == 1) stockham_pass<2, BPT>(buf, M, Ns, tid, NT);
+        if constexpr (L == 3) stockham_pass<8, BPT>(buf, M, Ns, tid, NT, tw);
+        else if constexpr (L == 2) stockham_pass<4, BPT>(buf, M, Ns, tid, NT, tw);
+        else if constexpr (L == 1) stockham_pass<2, BPT>(buf, M, Ns, tid, NT, tw);
     } else {
         const int left = lm & 3;
         if (left > 0) {
             const int nb = M >> left;
             const int bpt = nb > NT ? nb / NT : 1;
             if (left == 3) {
-                if (bpt == 1) stockham_pass<8, 1>(buf, M, Ns, tid, NT);
-                else stockham_pass<8, 2>(buf, M, Ns, tid, NT);
+                if (bpt == 1) stockham_pass<8, 1>(buf, M, Ns, tid, NT, tw);
+                else stockham_pass<8, 2>(buf, M, Ns, tid, NT, tw);
             } else if (left == 2) {
-                if (bpt == 1) stockham_pass<4, 1>(buf, M, Ns, tid, NT);
-                else if (bpt == 2) stockham_pass<4, 2>(buf, M, Ns, tid, NT);
-                else stockham_pass<4, 4>(buf, M, Ns, tid, NT);
+                if (bpt == 1) stockham_pass<4, 1>(buf, M, Ns, tid, NT, tw);
+                else if (bpt == 2) stockham_pass<4, 2>(buf, M, Ns, tid, NT, tw);
+                else stockham_pass<4, 4>(buf, M, Ns, tid, NT, tw);
             } else {
-                if (bpt == 1) stockham_pass<2, 1>(buf, M, Ns, tid, NT);
-                else if (bpt == 2) stockham_pass<2, 2>(buf, M, Ns, tid, NT);
-                else if (bpt == 4) stockham_pass<2, 4>(buf, M, Ns, tid, NT);
-                else stockham_pass<2, 8>(buf, M, Ns, tid, NT);
+                if (bpt == 1) stockham_pass<2, 1>(buf, M, Ns, tid, NT, tw);
+                else if (bpt == 2) stockham_pass<2, 2>(buf, M, Ns, tid, NT, tw);
+                else if (bpt == 4) stockham_pass<2, 4>(buf, M, Ns, tid, NT, tw);
+                else stockham_pass<2, 8>(buf, M, Ns, tid, NT, tw);
             }
         }
+    }
+}
+
+// Roots of unity omega_M^t = e^{-2 pi i t / M} for t < M / 2 as the product
+// tw[t mod 64] tw[64 + t / 64]: 128 entries (2 KB of LDS) per workgroup,
+// written before the workgroup's first FFT (callers place a barrier between).
+template <int NT>
+__device__ __forceinline__ void root_table(double2* tw, int M, int tid) {
+    for (int i = tid; i < 128; i += NT) {
+        const int e = i < 64 ? i : (i - 64) * 64;
+        double sn, cs;
+        sincospi(-2.0 * e / M, &sn, &cs);
+        tw[i] = make_double2(cs, sn);
     }
 }
 
@@ -307,6 +321,7 @@ template <int NT, int J, int MFIX>
 __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     extern __shared__ double2 buf[];
     __shared__ double2 red[NT / 64];
+    __shared__ double2 tw[128];
     const DevCtrl* ctrl = a.io.ctrl;
     if (ctrl && ctrl->done) return;
     const int q = a.qlist[blockIdx.x];
@@ -337,6 +352,7 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     constexpr int FB = NT >= 512 ? 5 : 6;
 
     const bool syn = (a.mode == RING_SYN || a.mode == RING_ITER || a.mode == RING_SYN_WRES);
+    root_table<NT>(tw, M, tid);  // read after the barrier that ends the input stage
     if (syn) {
         // Fold F into the DFT input x_k = conj(Z_k) [times conj(c_k)],
         // Z_k = H^N_k + i H^S_k, H_k = sum over m = k mod n of F_m e^{i m phi0}
@@ -457,7 +473,7 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     if (syn) {
 #pragma unroll 1
         for (int step = 0; step < (blue ? 2 : 1); ++step) {
-            fft<NT, MFIX>(buf, M, logM, tid);
+            fft<NT, MFIX>(buf, M, logM, tid, tw);
             if (blue && step == 0) {
                 filter_product<NT>(buf, M, B, tid);
                 lds_barrier();
@@ -539,7 +555,7 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     }
 #pragma unroll 1
     for (int step = 0; step < (blue ? 2 : 1); ++step) {
-        fft<NT, MFIX>(buf, M, logM, tid);
+        fft<NT, MFIX>(buf, M, logM, tid, tw);
         if (blue && step == 0) {
             filter_product<NT>(buf, M, B, tid);
             lds_barrier();
@@ -599,6 +615,7 @@ __global__ __launch_bounds__(NT) void k_chirp_spectrum(const int* __restrict__ q
                                                        const double2* __restrict__ chirp,
                                                        double2* __restrict__ bspec) {
     extern __shared__ double2 buf[];
+    __shared__ double2 tw[128];
     const int q = qlist[blockIdx.x];
     const int n = nph[q], M = Mq[q];
     const int logM = 31 - __clz(M);
@@ -609,8 +626,9 @@ __global__ __launch_bounds__(NT) void k_chirp_spectrum(const int* __restrict__ q
         else if (M - t < n) v = ch[M - t];
         buf[pad(t)] = v;
     }
+    root_table<NT>(tw, M, threadIdx.x);
     lds_barrier();
-    fft<NT, 0>(buf, M, logM, threadIdx.x);
+    fft<NT, 0>(buf, M, logM, threadIdx.x, tw);
     for (int k = threadIdx.x; k < M; k += NT) bspec[boff[q] + k] = buf[pad(k)];
 }
 
