@@ -144,7 +144,10 @@ dmwf_status dmwf_dm_iterate(dmwf_plan* plan, double xi, double alpha, const doub
 
 /* Full solve for every map of the plan.  Outputs the Wiener filter a_lm and
  * map s_WF = Y a_WF.  Cold start from a = 0 unless sched->start_final.  The
- * host synchronises the stream once per iteration to read the Cauchy ratio.
+ * level decisions (Cauchy ratio against each level's tolerance, the next xi,
+ * the stop) are taken on the device after every iteration; the host enqueues
+ * iterations in batches and synchronises with the stream once per batch.
+ * The schedule may have at most 1024 levels (else DMWF_ERR_INVALID_ARG).
  * stats may be NULL; with nmaps > 1 it describes the last map.
  * Returns DMWF_ERR_NONFINITE for NaN/Inf or negative values in d, N^-1 or
  * C_l (checked on the device before the first iteration) or a NaN Cauchy

@@ -180,3 +180,84 @@ def test_solve_error_paths():
                             d_t.data_ptr(), w_t.data_ptr(), alm.data_ptr(), out.data_ptr(),
                             out.data_ptr(), 1, plan.ws.data_ptr(), plan.ws_bytes, None)
     assert s == b.ERR_INVALID_ARG
+
+
+def test_solve_replays_oracle_schedule():
+    """The device-side level control honours replayed per-level counts: the
+    oracle decides its own stops, the GPU replays them and lands on the same
+    iterate."""
+    dev = device()
+    nside = 8
+    p, T, d, w = _cfg1(nside)
+    ref = dm.solve(T, d, w, p.cl, eps_final=1e-9, eps_coarse=1e-4)
+    plan = _plan(nside, p.lmax)
+    alm, smap, st = plan.solve(to_dev(p.cl, dev), to_dev(d, dev), to_dev(w, dev),
+                               eps_final=1e-9, eps_coarse=1e-4, replay=ref.iters_per_level)
+    assert st.status == 0
+    assert st.iters_per_level == list(ref.iters_per_level)
+    assert st.n_iter == ref.n_iter
+    assert rel(alm.cpu().numpy(), ref.alm) < 1e-10
+    assert rel(smap.cpu().numpy(), ref.map) < 1e-10
+
+
+def test_solve_iteration_cap_inside_a_level():
+    """A cap that falls in the middle of a level stops there: the counts of the
+    levels run add up to the cap and the state is the oracle's after as many
+    iterations."""
+    dev = device()
+    nside = 8
+    p, T, d, w = _cfg1(nside)
+    plan = _plan(nside, p.lmax)
+    full = dm.solve(T, d, w, p.cl, eps_final=1e-8, eps_coarse=1e-4)
+    cap = full.iters_per_level[0] + full.iters_per_level[1] + 2
+    alm, smap, st = plan.solve(to_dev(p.cl, dev), to_dev(d, dev), to_dev(w, dev),
+                               eps_final=1e-8, eps_coarse=1e-4, max_iter=cap)
+    from paper_1702_08852_amd import dmwf as b
+    assert st.status == b.ERR_NOT_CONVERGED
+    assert st.n_iter == cap and sum(st.iters_per_level) == cap
+    # the oracle replays the completed levels and is cut by the same cap on the
+    # last one (its count there is set beyond the cap)
+    nrest = len(full.iters_per_level) - len(st.iters_per_level)
+    replay = st.iters_per_level[:-1] + [st.iters_per_level[-1] + 1000] + [1] * nrest
+    ref = dm.solve(T, d, w, p.cl, eps_final=1e-8, eps_coarse=1e-4, replay=replay, max_iter=cap)
+    assert ref.n_iter == cap and not ref.converged
+    assert rel(alm.cpu().numpy(), ref.alm) < 1e-10
+
+
+def test_solve_two_maps_match_single_map_solves():
+    """A plan with two maps solves them one after the other, each exactly as a
+    single-map plan would."""
+    import torch
+    dev = device()
+    nside = 8
+    p, T, d, w = _cfg1(nside)
+    d2 = np.roll(d, 37)
+    w2 = np.roll(w, 37)
+    cl2 = p.cl * 2.0
+    single = _plan(nside, p.lmax)
+    a1, s1, _ = single.solve(to_dev(p.cl, dev), to_dev(d, dev), to_dev(w, dev), eps_final=1e-8)
+    a1, s1 = a1.cpu().numpy(), s1.cpu().numpy()
+    a2, s2, _ = single.solve(to_dev(cl2, dev), to_dev(d2, dev), to_dev(w2, dev), eps_final=1e-8)
+    a2, s2 = a2.cpu().numpy(), s2.cpu().numpy()
+    from paper_1702_08852_amd import Plan
+    two = Plan(nside, p.lmax, nmaps=2, device=dev)
+    cl_t = torch.tensor(np.stack([p.cl, cl2]), device=dev)
+    alm, smap, _ = two.solve(cl_t, torch.tensor(np.stack([d, d2]), device=dev),
+                             torch.tensor(np.stack([w, w2]), device=dev), eps_final=1e-8)
+    alm, smap = alm.cpu().numpy(), smap.cpu().numpy()
+    assert rel(alm[0], a1) < 1e-13 and rel(alm[1], a2) < 1e-13
+    assert rel(smap[0], s1) < 1e-13 and rel(smap[1], s2) < 1e-13
+
+
+def test_solve_rejects_schedules_beyond_the_level_table():
+    """More cooling levels than the device level table holds is an argument
+    error raised before any iteration runs."""
+    from paper_1702_08852_amd import DmwfError
+    from paper_1702_08852_amd import dmwf as b
+    dev = device()
+    nside = 4
+    p, T, d, w = _cfg1(nside)
+    plan = _plan(nside, p.lmax)
+    with pytest.raises(DmwfError) as e:
+        plan.solve(to_dev(p.cl, dev), to_dev(d, dev), to_dev(w, dev), beta=0.9999)
+    assert e.value.status == b.ERR_INVALID_ARG
