@@ -1055,14 +1055,28 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
             DMWF_HIP(hipEventRecord(p->batch_ev[slot], s));
             return DMWF_OK;
         };
+        // never more iterations than the cap allows, nor (replaying) than the
+        // replayed counts add up to: a replayed solve enqueues exactly its
+        // iterations
+        long long budget = sc->max_iter;
+        if (sc->replay_iters) {
+            long long sum = 0;
+            for (int k = 0; k < nl; ++k) sum += std::max(1, sc->replay_iters[k]);
+            budget = std::min(budget, sum);
+        }
+        long long launched = 0;
         int batch = 4, cur = 0;
-        st = enqueue(batch, cur);
+        int nb = (int)std::min<long long>(batch, budget);
+        st = enqueue(nb, cur);
         if (st != DMWF_OK) return st;
+        launched += nb;
         DevCtrl fin{};
         while (true) {
             batch = std::min(2 * batch, 64);
-            st = enqueue(batch, cur ^ 1);
+            nb = (int)std::min<long long>(batch, budget - launched);
+            st = enqueue(nb, cur ^ 1);
             if (st != DMWF_OK) return st;
+            launched += nb;
             DMWF_HIP(hipEventSynchronize(p->batch_ev[cur]));
             if (p->h_ctrl[cur].done) {
                 DMWF_HIP(hipEventSynchronize(p->batch_ev[cur ^ 1]));
