@@ -224,9 +224,25 @@ CONFIGS = {
     "cfg1": 1,   # Nside 16, lmax 32: C_l = 1/(l(l+1)), lognormal noise, |b|<10 + 10 holes of 5 deg
     "cfg2": 2,   # Nside 256, lmax 512: damped spectrum, ecliptic hits, |b|<15 + 200 holes of 1 deg
     "cfg3": 3,   # Nside 1024, lmax 2048: as cfg2, sigma0 45 uK, 20% masked (band + 2000 holes of 0.3 deg)
+    "cfg4": 4,   # batch member: damped spectrum, own |b| cut 5-20 deg + 50-500 holes of 1 deg,
+                 # sigma0 ~ U[10, 60] uK times a lognormal(0, 0.25) per-pixel modulation
 }
 
-DEFAULT_NSIDE = {"cfg1": 16, "cfg2": 256, "cfg3": 1024}
+DEFAULT_NSIDE = {"cfg1": 16, "cfg2": 256, "cfg3": 1024, "cfg4": 128}
+
+# The batched workload: maps per Nside (lmax = 2 Nside), 96 in all.
+BATCH_GROUPS = ((128, 48), (256, 32), (512, 16))
+
+
+def batch_members(nside: int):
+    """Map indices of the batched workload that have this Nside (each member
+    draws its own mask and noise from its index)."""
+    start = 0
+    for ns, cnt in BATCH_GROUPS:
+        if ns == nside:
+            return list(range(start, start + cnt))
+        start += cnt
+    raise KeyError(nside)
 
 
 def make_problem(name: str, nside: int | None = None, lmax: int | None = None,
@@ -266,6 +282,17 @@ def make_problem(name: str, nside: int | None = None, lmax: int | None = None,
             meta.update(bcut_deg=bcut, holes=2000, hole_deg=0.3, hole_fraction=float(holes.mean()))
         eps = 1e-6
         meta.update(sigma0_uK=sigma0, noise="sigma0/sqrt(1+4cos^2(beta_ecl))")
+    elif name == "cfg4":
+        r_par = _rng(cid, index, "params")
+        cl = cl_damped(lmax)
+        sigma0 = float(r_par.uniform(10.0, 60.0))
+        bcut = float(r_par.uniform(5.0, 20.0))
+        nholes = int(r_par.integers(50, 501))
+        sigma = sigma0 * np.exp(r_sig.normal(0.0, 0.25, npix))
+        mask = band_mask(nside, bcut) | hole_mask(nside, nholes, 1.0, r_hol)
+        eps = 1e-6
+        meta.update(sigma0_uK=sigma0, bcut_deg=bcut, holes=nholes, hole_deg=1.0,
+                    noise="sigma0*exp(N(0,0.25))")
     else:  # pragma: no cover
         raise KeyError(name)
     alm = draw_alm(cl, r_alm)

@@ -65,7 +65,7 @@ typedef struct dmwf_plan dmwf_plan;
 typedef struct {
     int nside;     /* power of two, 1 .. 8192                                  */
     int lmax;      /* 0 .. 3 nside - 1                                         */
-    int nmaps;     /* >= 1; maps are processed one after another             */
+    int nmaps;     /* >= 1; the maps of a plan are transformed and solved together */
     int precision; /* DMWF_FP64                                                */
 } dmwf_plan_desc;
 
@@ -113,7 +113,7 @@ void dmwf_plan_destroy(dmwf_plan* plan);
 /* Workspace size in bytes needed by every call on this plan. */
 dmwf_status dmwf_workspace_bytes(const dmwf_plan* plan, size_t* bytes);
 
-/* Synthesis F^-1: map = Y alm for each of the plan's maps. */
+/* Synthesis F^-1: map = Y alm for each of the plan's maps (one batched pass). */
 dmwf_status dmwf_alm2map(dmwf_plan* plan, const double* dev_alm, double* dev_map,
                          void* dev_ws, size_t ws_bytes, void* stream);
 
@@ -147,13 +147,18 @@ dmwf_status dmwf_dm_iterate(dmwf_plan* plan, double xi, double alpha, const doub
  * level decisions (Cauchy ratio against each level's tolerance, the next xi,
  * the stop) are taken on the device after every iteration; the host enqueues
  * iterations in batches and synchronises with the stream once per batch.
- * The schedule may have at most 1024 levels (else DMWF_ERR_INVALID_ARG).
- * stats may be NULL; with nmaps > 1 it describes the last map.
+ * The maps of the plan iterate together, one launch per stage for all of
+ * them, each with its own alpha, schedule, level and stop; a map that has
+ * stopped is left untouched while the others go on.  Every map comes out
+ * exactly as a one-map plan would compute it.  A schedule may have at most
+ * 1024 levels (else DMWF_ERR_INVALID_ARG); with replay_iters, every map's
+ * schedule must have n_replay levels.  stats may be NULL or point to nmaps
+ * records, one per map.
  * Returns DMWF_ERR_NONFINITE for NaN/Inf or negative values in d, N^-1 or
- * C_l (checked on the device before the first iteration) or a NaN Cauchy
- * ratio, DMWF_ERR_INVALID_ARG if every pixel of a map is masked, and
- * DMWF_ERR_NOT_CONVERGED after max_iter iterations (outputs hold the last
- * iterate). */
+ * C_l of any map (checked on the device before the first iteration) or a NaN
+ * Cauchy ratio, DMWF_ERR_INVALID_ARG if every pixel of a map is masked, and
+ * DMWF_ERR_NOT_CONVERGED if some map ran max_iter iterations (outputs hold
+ * the last iterate); dmwf_last_error() names the map. */
 dmwf_status dmwf_solve(dmwf_plan* plan, const double* dev_cl, const double* dev_d,
                        const double* dev_ninv, const dmwf_schedule* sched,
                        double* dev_alm_out, double* dev_map_out, dmwf_stats* stats,

@@ -81,13 +81,17 @@ __global__ void k_ell_from_cl(const double* __restrict__ cl, int lmax, double mu
     }
 }
 
-// a'_lm = g_lm a_lm (synthesis input), Im a_l0 dropped.  grid (l blocks, m).
-__global__ void k_prep_syn(const double2* __restrict__ alm, const double* __restrict__ g,
-                           double2* __restrict__ ap, int lmax) {
+// a'_lm = g_lm a_lm (synthesis input), Im a_l0 dropped.  grid (l blocks, m,
+// map); map k reads alm + k * alm_map and writes ap + k * ap_map.
+__global__ void k_prep_syn(const double2* __restrict__ alm, long long alm_map,
+                           const double* __restrict__ g, double2* __restrict__ ap,
+                           long long ap_map, int lmax) {
     const int m = blockIdx.y;
     const int l = m + blockIdx.x * blockDim.x + threadIdx.x;
     if (l > lmax) return;
     const long long i = alm_base(m, lmax) + l;
+    alm += blockIdx.z * alm_map;
+    ap += blockIdx.z * ap_map;
     double2 v = alm[i];
     if (m == 0) v.y = 0.0;
     ap[i] = make_double2(g[i] * v.x, g[i] * v.y);
@@ -97,32 +101,53 @@ __global__ void k_prep_syn(const double2* __restrict__ alm, const double* __rest
 //   b = Omega g_lm sum_chunks part,  a <- f_l (a + b),  a' = g_lm a,
 //   f_l = S_bar_l / (S_bar_l + xi/sigma),  S_bar_l = max(C_l - mu, 0).
 // Slots with l > l_iter are set to zero without reading the partial sums.
-// With ctrl (the solve loop) mu and xi / sigma are the current level's, and
-// nothing runs once the solve has stopped.
-__global__ void k_diag(double2* __restrict__ a, double2* __restrict__ ap,
-                       const double2* __restrict__ part, int nchunk, size_t stride,
-                       const double* __restrict__ g, const double* __restrict__ cl, double mu,
-                       double xi_over_sigma, double omega, const int* __restrict__ ell_dev,
-                       int lmax, const DevCtrl* __restrict__ ctrl) {
-    if (ctrl) {
-        if (ctrl->done) return;
-        mu = ctrl->mu;
-        xi_over_sigma = ctrl->xi_over_sigma;
+// grid (l blocks, m, map).  With ctrl (the solve loop) mu and xi / sigma are
+// the map's current level's, and nothing runs once its solve has stopped.
+struct DiagArgs {
+    double2* a;             // state of map 0; map k at a + k * a_map
+    long long a_map;
+    double2* ap;            // g-scaled copy, map k at ap + k * ap_map
+    long long ap_map;
+    const double2* part;    // partials: chunk c of map k at part + k * part_map + c * stride
+    long long part_map;
+    size_t stride;
+    int nchunk;
+    const double* g;
+    const double* cl;       // C_l of map k at cl + k * (lmax + 1)
+    double mu, xi_over_sigma, omega;
+    const int* ell;         // l_iter of map k at ell[k * ell_stride]
+    int ell_stride;
+    int lmax;
+    const DevCtrl* ctrl;
+};
+
+__global__ void k_diag(DiagArgs d) {
+    const int k = blockIdx.z;
+    double mu = d.mu, xi_over_sigma = d.xi_over_sigma;
+    if (d.ctrl) {
+        const DevCtrl* c = d.ctrl + k;
+        if (c->done) return;
+        mu = c->mu;
+        xi_over_sigma = c->xi_over_sigma;
     }
     const int m = blockIdx.y;
     const int l = m + blockIdx.x * blockDim.x + threadIdx.x;
+    const int lmax = d.lmax;
     if (l > lmax) return;
-    const int ell = *ell_dev;
+    const int ell = d.ell[k * d.ell_stride];
     const long long i = alm_base(m, lmax) + l;
+    double2* a = d.a + k * d.a_map;
+    const double2* part = d.part + k * d.part_map;
+    const double* cl = d.cl + (long long)k * (lmax + 1);
     double2 out = make_double2(0.0, 0.0);
     if (l <= ell) {
         double sr = 0.0, si = 0.0;
-        for (int c = 0; c < nchunk; ++c) {
-            const double2 v = part[c * stride + i];
+        for (int c = 0; c < d.nchunk; ++c) {
+            const double2 v = part[c * d.stride + i];
             sr += v.x;
             si += v.y;
         }
-        const double sc = omega * g[i];
+        const double sc = d.omega * d.g[i];
         double sbar = cl[l] - mu;
         sbar = sbar > 0.0 ? sbar : 0.0;
         const double f = sbar / (sbar + xi_over_sigma);
@@ -131,16 +156,20 @@ __global__ void k_diag(double2* __restrict__ a, double2* __restrict__ ap,
         if (m == 0) out.y = 0.0;
     }
     a[i] = out;
-    ap[i] = make_double2(g[i] * out.x, g[i] * out.y);
+    d.ap[k * d.ap_map + i] = make_double2(d.g[i] * out.x, d.g[i] * out.y);
 }
 
-// out_lm = scale g_lm sum_chunks part (the adjoint), all l.
-__global__ void k_adj_final(const double2* __restrict__ part, int nchunk, size_t stride,
-                            const double* __restrict__ g, double2* __restrict__ out, double scale,
+// out_lm = scale g_lm sum_chunks part (the adjoint), all l.  grid (l blocks,
+// m, map): map k sums part + k * part_map into out + k * out_map.
+__global__ void k_adj_final(const double2* __restrict__ part, long long part_map, int nchunk,
+                            size_t stride, const double* __restrict__ g,
+                            double2* __restrict__ out, long long out_map, double scale,
                             int lmax) {
     const int m = blockIdx.y;
     const int l = m + blockIdx.x * blockDim.x + threadIdx.x;
     if (l > lmax) return;
+    part += blockIdx.z * part_map;
+    out += blockIdx.z * out_map;
     const long long i = alm_base(m, lmax) + l;
     double sr = 0.0, si = 0.0;
     for (int c = 0; c < nchunk; ++c) {
@@ -152,12 +181,16 @@ __global__ void k_adj_final(const double2* __restrict__ part, int nchunk, size_t
     out[i] = make_double2(sc * sr, m == 0 ? 0.0 : sc * si);
 }
 
-// m bound of ring pair q at the l_iter of every level: mhi_tab[k][q].
+// m bound of ring pair q at the l_iter of every level: mhi_tab[k][q], for
+// the levels of map blockIdx.y (its table at mhi_tab + map * kMaxLevels * nq).
 __global__ void k_level_tab(const int* __restrict__ lsmin, int nq, int lmax,
-                            const DevLevel* __restrict__ levels, int nlev,
+                            const DevLevel* __restrict__ levels, const DevCtrl* __restrict__ ctrl,
                             int* __restrict__ mhi_tab) {
+    const int map = blockIdx.y;
     const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i >= (long long)nlev * nq) return;
+    if (i >= (long long)ctrl[map].nlev * nq) return;
+    levels += (size_t)map * kMaxLevels;
+    mhi_tab += (size_t)map * kMaxLevels * nq;
     const int k = (int)(i / nq), q = (int)(i % nq);
     const int ell = levels[k].ell;
     const int* row = lsmin + (size_t)q * (lmax + 1);
@@ -186,29 +219,40 @@ __device__ void ctrl_enter_level(DevCtrl* c, const DevLevel* levels, int k, int*
     *ell_ana_out = levels[k].ell_next;
 }
 
-__global__ void k_ctrl_init(DevCtrl* c, const DevLevel* levels, int nlev, int max_iter,
-                            int replay, int* ell_out, int* ell_ana_out, int* lev_iters) {
-    c->done = 0;
-    c->status = 0;
-    c->total = 0;
-    c->nlev = nlev;
-    c->max_iter = max_iter;
-    c->replay = replay;
-    c->ratio = 0.0;
-    for (int k = 0; k < nlev; ++k) lev_iters[k] = 0;
-    ctrl_enter_level(c, levels, 0, ell_out, ell_ana_out);
+// Pointers of map k in the solve loop's per-map device state.
+struct CtrlMaps {
+    DevCtrl* ctrl;          // [maps]
+    const DevLevel* levels; // [maps][kMaxLevels]
+    int* lev_iters;         // [maps][kMaxLevels]
+    int* ell;               // [maps] l_iter
+    int* ell_ana;           // [maps] analysis band of the ring stage
+};
+
+// One block per map: the control block (uploaded with nlev, max_iter, replay
+// and alpha set) enters level 0.
+__global__ void k_ctrl_init(CtrlMaps cm) {
+    const int k = blockIdx.x;
+    DevCtrl* c = cm.ctrl + k;
+    const DevLevel* lv = cm.levels + (size_t)k * kMaxLevels;
+    int* its = cm.lev_iters + (size_t)k * kMaxLevels;
+    for (int i = threadIdx.x; i < c->nlev; i += blockDim.x) its[i] = 0;
+    if (threadIdx.x == 0) ctrl_enter_level(c, lv, 0, cm.ell + k, cm.ell_ana + k);
 }
 
-// After each iteration of the solve loop (one block): the Cauchy sums over
-// the ring pairs in a fixed order, the ratio ||s_i - s_{i-1}|| / ||s_i||, and
-// the schedule's decision: stay on the level, move to the next one (a
-// level's tolerance met, or its replayed count reached), or stop (the last
-// level met its tolerance, the iteration cap, or a NaN ratio).
-__global__ void k_control(const double* __restrict__ cpart, int n, DevCtrl* c,
-                          const DevLevel* __restrict__ levels, int* lev_iters, int* ell_out,
-                          int* ell_ana_out, double* out2) {
+// After each iteration of the solve loop (one block per map): the map's
+// Cauchy sums over the ring pairs in a fixed order, the ratio
+// ||s_i - s_{i-1}|| / ||s_i||, and the schedule's decision: stay on the
+// level, move to the next one (a level's tolerance met, or its replayed count
+// reached), or stop (the last level met its tolerance, the iteration cap, or
+// a NaN ratio).
+__global__ void k_control(const double* __restrict__ cpart_all, int n, CtrlMaps cm,
+                          double* out2_all) {
     __shared__ double sa[256], sb[256];
+    const int map = blockIdx.x;
+    DevCtrl* c = cm.ctrl + map;
     if (c->done) return;
+    const double* cpart = cpart_all + (size_t)map * 2 * n;
+    const DevLevel* levels = cm.levels + (size_t)map * kMaxLevels;
     double a = 0.0, b = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         a += cpart[2 * i];
@@ -226,6 +270,7 @@ __global__ void k_control(const double* __restrict__ cpart, int n, DevCtrl* c,
     }
     if (threadIdx.x != 0) return;
     const double num = sa[0], den = sb[0];
+    double* out2 = out2_all + (size_t)map * 4;
     out2[0] = num;
     out2[1] = den;
     const double ratio = den > 0.0 ? sqrt(num / den) : (num == 0.0 ? 0.0 : INFINITY);
@@ -233,7 +278,7 @@ __global__ void k_control(const double* __restrict__ cpart, int n, DevCtrl* c,
     c->it_level += 1;
     c->total += 1;
     const int k = c->level;
-    lev_iters[k] = c->it_level;
+    cm.lev_iters[(size_t)map * kMaxLevels + k] = c->it_level;
     if (isnan(ratio)) {
         c->status = 2;
         c->done = 1;
@@ -245,7 +290,7 @@ __global__ void k_control(const double* __restrict__ cpart, int n, DevCtrl* c,
             c->status = 0;
             c->done = 1;
         } else {
-            ctrl_enter_level(c, levels, k + 1, ell_out, ell_ana_out);
+            ctrl_enter_level(c, levels, k + 1, cm.ell + map, cm.ell_ana + map);
         }
         return;
     }
@@ -259,6 +304,10 @@ __global__ void k_zero2(double2* p, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
         p[i] = make_double2(0.0, 0.0);
+}
+
+__global__ void k_set_ints(int* p, int n, int v) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
 }
 
 // Sum per-ring-pair pairs (num, den) into out[2] (one block, fixed order).
@@ -285,11 +334,16 @@ __global__ void k_sum_pairs(const double* __restrict__ part, int n, double* __re
     }
 }
 
-// Input screening: flags |= 1 non-finite d, 2 negative or non-finite N^-1,
-// 4 negative or non-finite C_l.  Per-block max of N^-1 into bmax[block].
+// Input screening, grid (kCheckBlocks, map): flags[map] |= 1 non-finite d,
+// 2 negative or non-finite N^-1, 4 negative or non-finite C_l.  Per-block
+// max of N^-1 into bmax[map][block].
 __global__ void k_check(const double* __restrict__ d, const double* __restrict__ w, long long n,
                         const double* __restrict__ cl, int L, int* flags, double* bmax) {
     __shared__ double sm[256];
+    const int map = blockIdx.y;
+    d += map * n;
+    w += map * n;
+    cl += (long long)map * L;
     int f = 0;
     double mx = 0.0;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -303,18 +357,20 @@ __global__ void k_check(const double* __restrict__ d, const double* __restrict__
         for (int l = threadIdx.x; l < L; l += blockDim.x)
             if (!isfinite(cl[l]) || cl[l] < 0.0) f |= 4;
     }
-    if (f) atomicOr(flags, f);
+    if (f) atomicOr(flags + map, f);
     sm[threadIdx.x] = mx;
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) bmax[blockIdx.x] = sm[0];
+    if (threadIdx.x == 0) bmax[(size_t)map * gridDim.x + blockIdx.x] = sm[0];
 }
 
-__global__ void k_max_final(const double* __restrict__ bmax, int n, double* out) {
+// One block per map: out[map * out_map] = max over the map's block maxima.
+__global__ void k_max_final(const double* __restrict__ bmax, int n, double* out, int out_map) {
     __shared__ double sm[256];
+    bmax += (size_t)blockIdx.x * n;
     double mx = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) mx = fmax(mx, bmax[i]);
     sm[threadIdx.x] = mx;
@@ -323,7 +379,7 @@ __global__ void k_max_final(const double* __restrict__ bmax, int n, double* out)
         if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = sm[0];
+    if (threadIdx.x == 0) out[(size_t)blockIdx.x * out_map] = sm[0];
 }
 
 // Residual of the whitened Wiener filter equation (paper Appendix C form):
@@ -369,22 +425,39 @@ __global__ void k_resid_norms(const double2* __restrict__ a, const double2* __re
 // ---------------------------------------------------------------------------
 struct Ws {
     char* base;
-    double2* spec() const { return reinterpret_cast<double2*>(base + off.spec); }
-    double2* part() const { return reinterpret_cast<double2*>(base + off.part); }
-    double2* ap() const { return reinterpret_cast<double2*>(base + off.ap); }
-    double2* aux() const { return reinterpret_cast<double2*>(base + off.aux); }
-    double* cpart() const { return reinterpret_cast<double*>(base + off.cpart); }
-    int* mhi() const { return reinterpret_cast<int*>(base + off.mhi); }
-    int* ell() const { return reinterpret_cast<int*>(base + off.scal); }
-    int* flags() const { return reinterpret_cast<int*>(base + off.scal + 4); }
-    int* ell_ana() const { return reinterpret_cast<int*>(base + off.scal + 8); }
+    int nmaps;
+    WsLayout off;
+    double2* spec(int k) const {
+        return reinterpret_cast<double2*>(base + off.spec) + k * off.spec_map;
+    }
+    double2* part(int k) const {
+        return reinterpret_cast<double2*>(base + off.part) + k * off.part_map;
+    }
+    double2* ap(int k) const { return reinterpret_cast<double2*>(base + off.ap) + k * off.alm_map; }
+    double2* aux(int k) const {
+        return reinterpret_cast<double2*>(base + off.aux) + k * off.alm_map;
+    }
+    double* cpart(int k, int nq) const {
+        return reinterpret_cast<double*>(base + off.cpart) + (size_t)k * 2 * nq;
+    }
+    int* mhi(int k, int nq) const { return reinterpret_cast<int*>(base + off.mhi) + (size_t)k * nq; }
+    int* ell(int k) const { return reinterpret_cast<int*>(base + off.ells) + k; }
+    int* ell_ana(int k) const { return reinterpret_cast<int*>(base + off.ells) + nmaps + k; }
+    int* flags(int k) const { return reinterpret_cast<int*>(base + off.ells) + 2 * nmaps + k; }
+    double* mdbl(int k) const { return reinterpret_cast<double*>(base + off.mdbl) + 4 * k; }
+    double* bmax() const { return reinterpret_cast<double*>(base + off.bmax); }
+    int* ell_full() const { return reinterpret_cast<int*>(base + off.scal); }
     double* out2() const { return reinterpret_cast<double*>(base + off.scal + 16); }
     double* scal_d() const { return reinterpret_cast<double*>(base + off.scal + 64); }
-    DevCtrl* ctrl() const { return reinterpret_cast<DevCtrl*>(base + off.ctrl); }
-    DevLevel* levels() const { return reinterpret_cast<DevLevel*>(base + off.levels); }
-    int* lev_iters() const { return reinterpret_cast<int*>(base + off.lev_iters); }
+    DevCtrl* ctrl(int k) const { return reinterpret_cast<DevCtrl*>(base + off.ctrl) + k; }
+    DevLevel* levels(int k) const {
+        return reinterpret_cast<DevLevel*>(base + off.levels) + (size_t)k * kMaxLevels;
+    }
+    int* lev_iters(int k) const {
+        return reinterpret_cast<int*>(base + off.lev_iters) + (size_t)k * kMaxLevels;
+    }
     int* mhi_tab() const { return reinterpret_cast<int*>(base + off.mhi_tab); }
-    WsLayout off;
+    CtrlMaps cmaps() const { return {ctrl(0), levels(0), lev_iters(0), ell(0), ell_ana(0)}; }
 };
 
 dmwf_status check_ws(const dmwf_plan* p, void* ws, size_t bytes, Ws* out) {
@@ -393,19 +466,24 @@ dmwf_status check_ws(const dmwf_plan* p, void* ws, size_t bytes, Ws* out) {
         return DMWF_ERR_WORKSPACE;
     }
     out->base = static_cast<char*>(ws);
+    out->nmaps = p->nmaps;
     out->off = p->ws;
     return DMWF_OK;
 }
 
-dim3 alm_grid(int lmax, int bs) { return dim3((lmax + 1 + bs - 1) / bs, lmax + 1); }
-
-// Number of blocks for per-pixel screening reductions (also the bmax length).
-constexpr int kCheckBlocks = 1024;
+dim3 alm_grid(int lmax, int bs, int nm = 1) {
+    return dim3((lmax + 1 + bs - 1) / bs, lmax + 1, nm);
+}
 
 size_t scal_bytes(const dmwf_plan* p) {
-    // ints + 2 doubles + block maxima + residual block sums
+    // ints + 2 doubles + residual block sums
     const size_t nres = 2 * (size_t)((p->lmax + 1 + 255) / 256) * (p->lmax + 1);
-    return 64 + sizeof(double) * (kCheckBlocks + 8 + nres);
+    return 64 + sizeof(double) * (8 + nres);
+}
+
+// Maps of a launch with one band limit for all (the shared int set to lmax).
+RingMaps ring_full(const dmwf_plan* p, const Ws& W, int nm) {
+    return RingMaps{nm, W.ell_full(), W.ell_full(), 0, p->d_mhi_full, p->d_mhi_full, 0};
 }
 
 }  // namespace
@@ -588,38 +666,54 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
     s = build_ring_tables(p);
     if (s != DMWF_OK) return fail(s);
 
-    // ---- workspace layout ----
+    // ---- workspace layout: per-map slices of every per-map region ----
     WsLayout& w = p->ws;
+    const size_t nm = (size_t)p->nmaps;
+    w.spec_map = (long long)p->lp * nq * 2;
+    w.part_map = (long long)p->nchunk_ana * ntab;
+    w.alm_map = (long long)ntab;
     size_t off = 0;
     w.spec = off;
-    off = align256(off + (size_t)p->lp * nq * 2 * sizeof(double2));
+    off = align256(off + nm * w.spec_map * sizeof(double2));
     w.part = off;
-    off = align256(off + (size_t)p->nchunk_ana * ntab * sizeof(double2));
+    off = align256(off + nm * w.part_map * sizeof(double2));
     w.ap = off;
-    off = align256(off + ntab * sizeof(double2));
+    off = align256(off + nm * w.alm_map * sizeof(double2));
     w.aux = off;
-    off = align256(off + ntab * sizeof(double2));
+    off = align256(off + nm * w.alm_map * sizeof(double2));
     w.cpart = off;
-    off = align256(off + (size_t)nq * 2 * sizeof(double));
+    off = align256(off + nm * nq * 2 * sizeof(double));
     w.mhi = off;
-    off = align256(off + (size_t)nq * sizeof(int));
+    off = align256(off + nm * nq * sizeof(int));
+    w.ells = off;
+    off = align256(off + 3 * nm * sizeof(int));
+    w.mdbl = off;
+    off = align256(off + 4 * nm * sizeof(double));
+    w.bmax = off;
+    off = align256(off + nm * kCheckBlocks * sizeof(double));
     w.scal = off;
     off = align256(off + scal_bytes(p));
     w.ctrl = off;
-    off = align256(off + sizeof(DevCtrl));
+    off = align256(off + nm * sizeof(DevCtrl));
     w.levels = off;
-    off = align256(off + kMaxLevels * sizeof(DevLevel));
+    off = align256(off + nm * kMaxLevels * sizeof(DevLevel));
     w.lev_iters = off;
-    off = align256(off + kMaxLevels * sizeof(int));
+    off = align256(off + nm * kMaxLevels * sizeof(int));
     w.mhi_tab = off;
-    off = align256(off + (size_t)kMaxLevels * nq * sizeof(int));
+    off = align256(off + nm * kMaxLevels * nq * sizeof(int));
     w.total = off;
-    if (hipHostMalloc((void**)&p->h_ctrl, 2 * sizeof(DevCtrl), hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc((void**)&p->h_ctrl, 2 * nm * sizeof(DevCtrl), hipHostMallocDefault) !=
+            hipSuccess ||
         hipEventCreateWithFlags(&p->batch_ev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->batch_ev[1], hipEventDisableTiming) != hipSuccess) {
         set_error("allocation of the solve-loop host buffer failed");
         return fail(DMWF_ERR_OOM);
     }
+    // maps per wave of the Legendre kernels until dmwf_autotune measures
+    // better: the synthesis shares its recurrence across up to four maps, the
+    // analysis (whose lane reduction grows with the maps) keeps one
+    p->syn_mb = p->nmaps >= 4 ? 4 : (p->nmaps >= 2 ? 2 : 1);
+    p->ana_mb = 1;
     *out = p;
     return DMWF_OK;
 }
@@ -677,25 +771,21 @@ dmwf_status dmwf_alm2map(dmwf_plan* p, const double* alm, double* map, void* ws,
     dmwf_status st = check_ws(p, ws, ws_bytes, &W);
     if (st != DMWF_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int k = 0; k < p->nmaps; ++k) {
-        const double2* a = reinterpret_cast<const double2*>(alm) + (size_t)k * p->nalm;
-        double* mp = map + (size_t)k * p->npix;
-        {
-            ProfScope ps(p, s, PROF_MISC);
-            hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell(), p->lmax);
-            hipLaunchKernelGGL(k_prep_syn, alm_grid(p->lmax, 256), dim3(256), 0, s, a, p->d_g,
-                               W.ap(), p->lmax);
-        }
-        DMWF_HIP(hipGetLastError());
-        st = launch_leg_syn(p, W.ap(), W.spec(), W.ell(), nullptr, s);
-        if (st != DMWF_OK) return st;
-        RingIO io{};
-        io.map_out = mp;
-        st = launch_ring(p, RING_SYN, W.spec(), W.ell(), W.ell(), p->d_mhi_full, p->d_mhi_full, io,
-                         s);
-        if (st != DMWF_OK) return st;
+    const int nm = p->nmaps;
+    {
+        ProfScope ps(p, s, PROF_MISC);
+        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell_full(), p->lmax);
+        hipLaunchKernelGGL(k_prep_syn, alm_grid(p->lmax, 256, nm), dim3(256), 0, s,
+                           reinterpret_cast<const double2*>(alm), p->nalm, p->d_g, W.ap(0),
+                           p->ws.alm_map, p->lmax);
     }
-    return DMWF_OK;
+    DMWF_HIP(hipGetLastError());
+    st = launch_leg_syn(p, W.ap(0), W.spec(0), LegMaps{nm, W.ell_full(), 0, nullptr}, p->syn_mb, s);
+    if (st != DMWF_OK) return st;
+    RingIO io{};
+    io.map_out = map;
+    io.pix_map = p->npix;
+    return launch_ring(p, RING_SYN, W.spec(0), ring_full(p, W, nm), io, s);
 }
 
 dmwf_status dmwf_adjoint(dmwf_plan* p, const double* map, double* alm, int scale_by_pixel_area,
@@ -708,28 +798,27 @@ dmwf_status dmwf_adjoint(dmwf_plan* p, const double* map, double* alm, int scale
     dmwf_status st = check_ws(p, ws, ws_bytes, &W);
     if (st != DMWF_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int k = 0; k < p->nmaps; ++k) {
-        double2* a = reinterpret_cast<double2*>(alm) + (size_t)k * p->nalm;
-        const double* mp = map + (size_t)k * p->npix;
-        {
-            ProfScope ps(p, s, PROF_MISC);
-            hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell(), p->lmax);
-        }
-        RingIO io{};
-        io.map_in = mp;
-        st = launch_ring(p, RING_ANA, W.spec(), W.ell(), W.ell(), p->d_mhi_full, p->d_mhi_full, io,
-                         s);
-        if (st != DMWF_OK) return st;
-        st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), nullptr, s);
-        if (st != DMWF_OK) return st;
-        {
-            ProfScope ps(p, s, PROF_DIAG);
-            hipLaunchKernelGGL(k_adj_final, alm_grid(p->lmax, 256), dim3(256), 0, s, W.part(),
-                               p->nchunk_ana, (size_t)p->nalm + kTablePad, p->d_g, a,
-                               scale_by_pixel_area ? p->omega : 1.0, p->lmax);
-        }
-        DMWF_HIP(hipGetLastError());
+    const int nm = p->nmaps;
+    {
+        ProfScope ps(p, s, PROF_MISC);
+        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell_full(), p->lmax);
     }
+    RingIO io{};
+    io.map_in = map;
+    io.pix_map = p->npix;
+    st = launch_ring(p, RING_ANA, W.spec(0), ring_full(p, W, nm), io, s);
+    if (st != DMWF_OK) return st;
+    st = launch_leg_ana(p, W.spec(0), W.part(0), LegMaps{nm, W.ell_full(), 0, nullptr}, p->ana_mb,
+                        s);
+    if (st != DMWF_OK) return st;
+    {
+        ProfScope ps(p, s, PROF_DIAG);
+        hipLaunchKernelGGL(k_adj_final, alm_grid(p->lmax, 256, nm), dim3(256), 0, s, W.part(0),
+                           p->ws.part_map, p->nchunk_ana, (size_t)p->nalm + kTablePad, p->d_g,
+                           reinterpret_cast<double2*>(alm), p->nalm,
+                           scale_by_pixel_area ? p->omega : 1.0, p->lmax);
+    }
+    DMWF_HIP(hipGetLastError());
     return DMWF_OK;
 }
 
@@ -738,87 +827,90 @@ dmwf_status dmwf_adjoint(dmwf_plan* p, const double* map, double* alm, int scale
 namespace dmwf {
 namespace {
 
-// The iteration body shared by dmwf_dm_iterate and the solve loop: harmonic
-// step from the residual spectrum in the workspace, synthesis, pixel step.
-// With ctrl (the solve loop) the level parameters come from the device
-// control block and the iteration ends with the level decision; without it
-// (dmwf_dm_iterate) they are the host values and the Cauchy sums go to
-// cauchy_out.
-dmwf_status iterate_body(dmwf_plan* p, const Ws& W, double xi, double alpha, double mu,
+// The iteration body shared by dmwf_dm_iterate (map 0, host parameters) and
+// the solve loop (every map, parameters from the per-map control blocks):
+// harmonic step from the residual spectrum in the workspace, synthesis,
+// pixel step.  The solve loop ends the iteration with each map's level
+// decision; dmwf_dm_iterate sums the Cauchy partials into cauchy_out.
+dmwf_status iterate_body(dmwf_plan* p, const Ws& W, int nm, double xi, double alpha, double mu,
                          const double* cl, const double* d, const double* w, double2* a,
                          double* s_map, int first_pix, const int* mhi_ana, double* cauchy_out,
                          DevCtrl* ctrl, hipStream_t s) {
-    const int* done = ctrl ? &ctrl->done : nullptr;
-    dmwf_status st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), done, s);
+    const LegMaps lm{nm, W.ell(0), 1, ctrl};
+    dmwf_status st = launch_leg_ana(p, W.spec(0), W.part(0), lm, p->ana_mb, s);
     if (st != DMWF_OK) return st;
     {
         ProfScope ps(p, s, PROF_DIAG);
-        hipLaunchKernelGGL(k_diag, alm_grid(p->lmax, 256), dim3(256), 0, s, a, W.ap(), W.part(),
-                           p->nchunk_ana, (size_t)p->nalm + kTablePad, p->d_g, cl, mu,
-                           xi * p->omega, p->omega, W.ell(), p->lmax,
-                           static_cast<const DevCtrl*>(ctrl));
+        DiagArgs da{a,       p->nalm, W.ap(0), p->ws.alm_map, W.part(0), p->ws.part_map,
+                    (size_t)p->nalm + kTablePad, p->nchunk_ana, p->d_g, cl, mu, xi * p->omega,
+                    p->omega, W.ell(0), 1, p->lmax, ctrl};
+        hipLaunchKernelGGL(k_diag, alm_grid(p->lmax, 256, nm), dim3(256), 0, s, da);
     }
     DMWF_HIP(hipGetLastError());
-    st = launch_leg_syn(p, W.ap(), W.spec(), W.ell(), done, s);
+    st = launch_leg_syn(p, W.ap(0), W.spec(0), lm, p->syn_mb, s);
     if (st != DMWF_OK) return st;
     RingIO io{};
     io.d = d;
     io.w = w;
     io.s_map = s_map;
-    io.cpart = W.cpart();
+    io.cpart = W.cpart(0, p->nq);
     io.xi = xi;
     io.alpha = alpha;
     io.first = first_pix;
     io.ctrl = ctrl;
     io.mhi_tab = W.mhi_tab();
-    st = launch_ring(p, RING_ITER, W.spec(), W.ell(), W.ell_ana(), W.mhi(), mhi_ana, io, s);
+    io.pix_map = p->npix;
+    const RingMaps rm{nm, W.ell(0), W.ell_ana(0), 1, W.mhi(0, p->nq), mhi_ana, 0};
+    st = launch_ring(p, RING_ITER, W.spec(0), rm, io, s);
     if (st != DMWF_OK) return st;
     {
         ProfScope ps(p, s, PROF_REDUCE);
         if (ctrl)
-            hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, s, W.cpart(), p->nq, ctrl,
-                               W.levels(), W.lev_iters(), W.ell(), W.ell_ana(), W.out2());
+            hipLaunchKernelGGL(k_control, dim3(nm), dim3(256), 0, s, W.cpart(0, p->nq), p->nq,
+                               W.cmaps(), W.mdbl(0));
         else
-            hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, s, W.cpart(), p->nq,
+            hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, s, W.cpart(0, p->nq), p->nq,
                                cauchy_out);
     }
     DMWF_HIP(hipGetLastError());
     return DMWF_OK;
 }
 
+// ||A x - y|| / ||y|| of one map (its C_l, d, N^-1, a); the workspace slices
+// of map 0 serve as scratch.
 dmwf_status residual_map(dmwf_plan* p, const Ws& W, const double* cl, const double* d,
                          const double* w, const double2* a, double* host_out, hipStream_t s) {
     // b1 = Y^H W (d - Y a) into ap (after its use as synthesis input), b2 = Y^H W d into aux
     {
         ProfScope ps(p, s, PROF_MISC);
-        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell(), p->lmax);
-        hipLaunchKernelGGL(k_prep_syn, alm_grid(p->lmax, 256), dim3(256), 0, s, a, p->d_g, W.ap(),
-                           p->lmax);
+        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell_full(), p->lmax);
+        hipLaunchKernelGGL(k_prep_syn, alm_grid(p->lmax, 256), dim3(256), 0, s, a, 0LL, p->d_g,
+                           W.ap(0), 0LL, p->lmax);
     }
     DMWF_HIP(hipGetLastError());
-    dmwf_status st = launch_leg_syn(p, W.ap(), W.spec(), W.ell(), nullptr, s);
+    const LegMaps lm{1, W.ell_full(), 0, nullptr};
+    dmwf_status st = launch_leg_syn(p, W.ap(0), W.spec(0), lm, 1, s);
     if (st != DMWF_OK) return st;
     RingIO io{};
     io.d = d;
     io.w = w;
-    st = launch_ring(p, RING_SYN_WRES, W.spec(), W.ell(), W.ell(), p->d_mhi_full, p->d_mhi_full, io,
-                     s);
+    st = launch_ring(p, RING_SYN_WRES, W.spec(0), ring_full(p, W, 1), io, s);
     if (st != DMWF_OK) return st;
-    st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), nullptr, s);
+    st = launch_leg_ana(p, W.spec(0), W.part(0), lm, 1, s);
     if (st != DMWF_OK) return st;
     const size_t stride = (size_t)p->nalm + kTablePad;
-    hipLaunchKernelGGL(k_adj_final, alm_grid(p->lmax, 256), dim3(256), 0, s, W.part(),
-                       p->nchunk_ana, stride, p->d_g, W.ap(), 1.0, p->lmax);
-    st = launch_ring(p, RING_ANA_WD, W.spec(), W.ell(), W.ell(), p->d_mhi_full, p->d_mhi_full, io,
-                     s);
+    hipLaunchKernelGGL(k_adj_final, alm_grid(p->lmax, 256), dim3(256), 0, s, W.part(0), 0LL,
+                       p->nchunk_ana, stride, p->d_g, W.ap(0), 0LL, 1.0, p->lmax);
+    st = launch_ring(p, RING_ANA_WD, W.spec(0), ring_full(p, W, 1), io, s);
     if (st != DMWF_OK) return st;
-    st = launch_leg_ana(p, W.spec(), W.part(), W.ell(), nullptr, s);
+    st = launch_leg_ana(p, W.spec(0), W.part(0), lm, 1, s);
     if (st != DMWF_OK) return st;
-    hipLaunchKernelGGL(k_adj_final, alm_grid(p->lmax, 256), dim3(256), 0, s, W.part(),
-                       p->nchunk_ana, stride, p->d_g, W.aux(), 1.0, p->lmax);
+    hipLaunchKernelGGL(k_adj_final, alm_grid(p->lmax, 256), dim3(256), 0, s, W.part(0), 0LL,
+                       p->nchunk_ana, stride, p->d_g, W.aux(0), 0LL, 1.0, p->lmax);
     const dim3 gr = alm_grid(p->lmax, 256);
-    double* bsum = W.scal_d() + kCheckBlocks + 8;
-    hipLaunchKernelGGL(k_resid_norms, gr, dim3(256), 0, s, a, W.ap(), W.aux(), cl, p->lmax, bsum);
+    double* bsum = W.scal_d();
+    hipLaunchKernelGGL(k_resid_norms, gr, dim3(256), 0, s, a, W.ap(0), W.aux(0), cl, p->lmax,
+                       bsum);
     const int nb = (int)(gr.x * gr.y);
     hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, s, bsum, nb, W.out2());
     DMWF_HIP(hipGetLastError());
@@ -857,18 +949,18 @@ dmwf_status dmwf_dm_iterate(dmwf_plan* p, double xi, double alpha, const double*
         // finds it complete
         ProfScope ps(p, s, PROF_MISC);
         hipLaunchKernelGGL(k_level, dim3((p->nq + 255) / 256), dim3(256), 0, s, cl, p->lmax, mu,
-                           p->d_lsmin, p->nq, W.ell(), W.ell_ana(), W.mhi());
+                           p->d_lsmin, p->nq, W.ell(0), W.ell_ana(0), W.mhi(0, p->nq));
     }
     DMWF_HIP(hipGetLastError());
     if (first) {
         RingIO io{};
         io.d = d;
         io.w = ninv;
-        st = launch_ring(p, RING_ANA_FIRST, W.spec(), W.ell_ana(), W.ell_ana(), p->d_mhi_full,
-                         p->d_mhi_full, io, s);
+        const RingMaps rm{1, W.ell_ana(0), W.ell_ana(0), 0, p->d_mhi_full, p->d_mhi_full, 0};
+        st = launch_ring(p, RING_ANA_FIRST, W.spec(0), rm, io, s);
         if (st != DMWF_OK) return st;
     }
-    return iterate_body(p, W, xi, alpha, mu, cl, d, ninv, reinterpret_cast<double2*>(alm_state),
+    return iterate_body(p, W, 1, xi, alpha, mu, cl, d, ninv, reinterpret_cast<double2*>(alm_state),
                         s_map, first ? 1 : 0, p->d_mhi_full, cauchy2, nullptr, s);
 }
 
@@ -900,221 +992,246 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
         set_error("schedule: need 0 < beta < 1, eps > 0, max_iter >= 1");
         return DMWF_ERR_INVALID_ARG;
     }
-    if (stats && stats->cap_levels < 0) {
-        set_error("stats.cap_levels < 0");
-        return DMWF_ERR_INVALID_ARG;
-    }
+    const int nm = p->nmaps;
+    if (stats)
+        for (int k = 0; k < nm; ++k)
+            if (stats[k].cap_levels < 0) {
+                set_error("stats.cap_levels < 0");
+                return DMWF_ERR_INVALID_ARG;
+            }
     Ws W;
     dmwf_status st = check_ws(p, ws, ws_bytes, &W);
     if (st != DMWF_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int L = p->lmax;
     const double sigma = 1.0 / p->omega;
-    dmwf_status result = DMWF_OK;
+    double2* a = reinterpret_cast<double2*>(alm_all);
 
-    for (int k = 0; k < p->nmaps; ++k) {
-        const double* cl = cl_all + (size_t)k * (L + 1);
-        const double* d = d_all + (size_t)k * p->npix;
-        const double* w = ninv_all + (size_t)k * p->npix;
-        double2* a = reinterpret_cast<double2*>(alm_all) + (size_t)k * p->nalm;
-        double* smap = map_all + (size_t)k * p->npix;
-
-        // a0: screen the inputs and find alpha = 1 / max N^-1
-        double* bmax = W.scal_d();
-        {
-            ProfScope ps(p, s, PROF_MISC);
-            hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.flags(), 0);
-            hipLaunchKernelGGL(k_check, dim3(kCheckBlocks), dim3(256), 0, s, d, w, p->npix, cl,
-                               L + 1, W.flags(), bmax);
-            hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, bmax, kCheckBlocks,
-                               W.out2());
-        }
-        DMWF_HIP(hipGetLastError());
-        int flags = 0;
-        double wmax = 0.0;
-        std::vector<double> hcl(L + 1);
-        DMWF_HIP(hipMemcpyAsync(&flags, W.flags(), sizeof(int), hipMemcpyDeviceToHost, s));
-        DMWF_HIP(hipMemcpyAsync(&wmax, W.out2(), sizeof(double), hipMemcpyDeviceToHost, s));
-        DMWF_HIP(hipMemcpyAsync(hcl.data(), cl, (L + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-        DMWF_HIP(hipStreamSynchronize(s));
-        if (flags) {
-            set_error("non-finite or negative values in d, N^-1 or C_l");
+    // a0: screen the inputs and find alpha = 1 / max N^-1, every map at once
+    {
+        ProfScope ps(p, s, PROF_MISC);
+        hipLaunchKernelGGL(k_set_ints, dim3(1), dim3(64), 0, s, W.flags(0), nm, 0);
+        hipLaunchKernelGGL(k_check, dim3(kCheckBlocks, nm), dim3(256), 0, s, d_all, ninv_all,
+                           p->npix, cl_all, L + 1, W.flags(0), W.bmax());
+        hipLaunchKernelGGL(k_max_final, dim3(nm), dim3(256), 0, s, W.bmax(), kCheckBlocks,
+                           W.mdbl(0) + 2, 4);
+    }
+    DMWF_HIP(hipGetLastError());
+    std::vector<int> flags(nm);
+    std::vector<double> md(4 * (size_t)nm);
+    std::vector<double> hcl((size_t)nm * (L + 1));
+    DMWF_HIP(hipMemcpyAsync(flags.data(), W.flags(0), nm * sizeof(int), hipMemcpyDeviceToHost, s));
+    DMWF_HIP(hipMemcpyAsync(md.data(), W.mdbl(0), md.size() * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+    DMWF_HIP(hipMemcpyAsync(hcl.data(), cl_all, hcl.size() * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+    DMWF_HIP(hipStreamSynchronize(s));
+    std::vector<double> alpha(nm);
+    for (int k = 0; k < nm; ++k) {
+        if (flags[k]) {
+            set_error("non-finite or negative values in d, N^-1 or C_l of map " +
+                      std::to_string(k));
             return DMWF_ERR_NONFINITE;
         }
+        const double wmax = md[4 * k + 2];
         if (!(wmax > 0.0)) {
-            set_error("every pixel is masked (N^-1 = 0 everywhere)");
+            set_error("every pixel of map " + std::to_string(k) + " is masked (N^-1 = 0)");
             return DMWF_ERR_INVALID_ARG;
         }
-        const double alpha = 1.0 / wmax;
+        alpha[k] = 1.0 / wmax;
+    }
 
-        // a1: the level schedule
+    // a1: the level schedule of every map
+    std::vector<std::vector<DevLevel>> lv(nm);
+    for (int k = 0; k < nm; ++k) {
+        const double* cl = hcl.data() + (size_t)k * (L + 1);
         double clmax = 0.0;
-        for (double v : hcl) clmax = std::max(clmax, v);
+        for (int l = 0; l <= L; ++l) clmax = std::max(clmax, cl[l]);
         std::vector<double> xis;
         if (sc->start_final) {
-            xis.push_back(alpha);
+            xis.push_back(alpha[k]);
         } else {
             const double mu0 = sc->mu0 < 0.0 ? beta * clmax : sc->mu0;
-            double xi = alpha + sigma * mu0;
-            while (xi > alpha) {
+            double xi = alpha[k] + sigma * mu0;
+            while (xi > alpha[k] && (int)xis.size() <= kMaxLevels) {
                 xis.push_back(xi);
                 xi = beta * xi;
             }
-            xis.push_back(alpha);
+            xis.push_back(alpha[k]);
         }
-        if (sc->replay_iters && sc->n_replay != (int)xis.size()) {
-            set_error("replay_iters has " + std::to_string(sc->n_replay) + " levels, schedule has " +
-                      std::to_string(xis.size()));
-            return DMWF_ERR_INVALID_ARG;
-        }
-
-        // start
-        int first_pix = 0;
-        if (sc->start_final) {
-            // s = Y a0, r = c (d - s) at xi = alpha
-            {
-                ProfScope ps(p, s, PROF_MISC);
-                hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell(), L);
-                hipLaunchKernelGGL(k_prep_syn, alm_grid(L, 256), dim3(256), 0, s, a, p->d_g,
-                                   W.ap(), L);
-            }
-            st = launch_leg_syn(p, W.ap(), W.spec(), W.ell(), nullptr, s);
-            if (st != DMWF_OK) return st;
-            RingIO io{};
-            io.map_out = smap;
-            st = launch_ring(p, RING_SYN, W.spec(), W.ell(), W.ell(), p->d_mhi_full, p->d_mhi_full,
-                             io, s);
-            if (st != DMWF_OK) return st;
-            io = RingIO{};
-            io.map_in = smap;
-            io.d = d;
-            io.w = w;
-            io.xi = alpha;
-            io.alpha = alpha;
-            st = launch_ring(p, RING_ANA_CRES, W.spec(), W.ell(), W.ell(), p->d_mhi_full,
-                             p->d_mhi_full, io, s);
-            if (st != DMWF_OK) return st;
-        } else {
-            {
-                ProfScope ps(p, s, PROF_MISC);
-                hipLaunchKernelGGL(k_zero2, dim3(256), dim3(256), 0, s, a, p->nalm);
-                hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell(), L);
-            }
-            RingIO io{};
-            io.d = d;
-            io.w = w;
-            st = launch_ring(p, RING_ANA_FIRST, W.spec(), W.ell(), W.ell(), p->d_mhi_full,
-                             p->d_mhi_full, io, s);
-            if (st != DMWF_OK) return st;
-            first_pix = 1;
-        }
-        DMWF_HIP(hipGetLastError());
-
-        // a1 / a6 on the device: the level table goes to the workspace, and
-        // after every iteration k_control takes the schedule's decision.  The
-        // host enqueues iterations in growing batches with two batches in
-        // flight and reads the control block once per batch, so the GPU never
-        // waits for the host; iterations enqueued after the stop do nothing.
         const int nl = (int)xis.size();
         if (nl > kMaxLevels) {
-            set_error("the schedule has " + std::to_string(nl) + " levels, more than " +
-                      std::to_string(kMaxLevels));
+            set_error("the schedule of map " + std::to_string(k) + " has more than " +
+                      std::to_string(kMaxLevels) + " levels");
             return DMWF_ERR_INVALID_ARG;
         }
-        std::vector<DevLevel> lv(nl);
-        for (int k = 0; k < nl; ++k) {
-            const double xi = xis[k], mu = (xi - alpha) / sigma;
+        if (sc->replay_iters && sc->n_replay != nl) {
+            set_error("replay_iters has " + std::to_string(sc->n_replay) + " levels, the schedule of map " +
+                      std::to_string(k) + " has " + std::to_string(nl));
+            return DMWF_ERR_INVALID_ARG;
+        }
+        lv[k].resize(nl);
+        for (int i = 0; i < nl; ++i) {
+            const double xi = xis[i], mu = (xi - alpha[k]) / sigma;
             int ell = -1;
             for (int l = 0; l <= L; ++l)
-                if (hcl[l] - mu > 0.0) ell = l;
-            lv[k] = DevLevel{xi,  mu, xi * p->omega, xi <= alpha ? sc->eps_final : sc->eps_coarse,
-                             ell, 0,  sc->replay_iters ? sc->replay_iters[k] : 0, 0};
+                if (cl[l] - mu > 0.0) ell = l;
+            lv[k][i] = DevLevel{xi,  mu, xi * p->omega, xi <= alpha[k] ? sc->eps_final : sc->eps_coarse,
+                                ell, 0,  sc->replay_iters ? sc->replay_iters[i] : 0, 0};
         }
-        for (int k = 0; k < nl; ++k) lv[k].ell_next = lv[std::min(k + 1, nl - 1)].ell;
-        DMWF_HIP(hipMemcpyAsync(W.levels(), lv.data(), nl * sizeof(DevLevel), hipMemcpyHostToDevice,
-                                s));
+        for (int i = 0; i < nl; ++i) lv[k][i].ell_next = lv[k][std::min(i + 1, nl - 1)].ell;
+    }
+
+    // a1 / a6 on the device: the level tables and control blocks go to the
+    // workspace, then every map enters its level 0
+    std::vector<DevCtrl> c0(nm);
+    int nl_max = 1;
+    for (int k = 0; k < nm; ++k) {
+        DevCtrl c{};
+        c.nlev = (int)lv[k].size();
+        c.max_iter = sc->max_iter;
+        c.replay = sc->replay_iters ? 1 : 0;
+        c.alpha = alpha[k];
+        c0[k] = c;
+        nl_max = std::max(nl_max, c.nlev);
+        DMWF_HIP(hipMemcpyAsync(W.levels(k), lv[k].data(), lv[k].size() * sizeof(DevLevel),
+                                hipMemcpyHostToDevice, s));
+    }
+    DMWF_HIP(hipMemcpyAsync(W.ctrl(0), c0.data(), nm * sizeof(DevCtrl), hipMemcpyHostToDevice, s));
+    {
+        ProfScope ps(p, s, PROF_MISC);
+        const long long nt = (long long)nl_max * p->nq;
+        hipLaunchKernelGGL(k_ctrl_init, dim3(nm), dim3(64), 0, s, W.cmaps());
+        hipLaunchKernelGGL(k_level_tab, dim3((unsigned)((nt + 255) / 256), nm), dim3(256), 0, s,
+                           p->d_lsmin, p->nq, L, W.levels(0), W.ctrl(0), W.mhi_tab());
+        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell_full(), L);
+    }
+    DMWF_HIP(hipGetLastError());
+
+    // start: r = d on unmasked pixels (cold), or r = c (d - Y a0) at xi = alpha
+    int first_pix = 0;
+    const RingMaps full = ring_full(p, W, nm);
+    if (sc->start_final) {
         {
             ProfScope ps(p, s, PROF_MISC);
-            const long long nt = (long long)nl * p->nq;
-            hipLaunchKernelGGL(k_level_tab, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s,
-                               p->d_lsmin, p->nq, L, W.levels(), nl, W.mhi_tab());
-            hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(1), 0, s, W.ctrl(), W.levels(), nl,
-                               sc->max_iter, sc->replay_iters ? 1 : 0, W.ell(), W.ell_ana(),
-                               W.lev_iters());
+            hipLaunchKernelGGL(k_prep_syn, alm_grid(L, 256, nm), dim3(256), 0, s, a, p->nalm,
+                               p->d_g, W.ap(0), p->ws.alm_map, L);
         }
-        DMWF_HIP(hipGetLastError());
-        auto enqueue = [&](int nit, int slot) -> dmwf_status {
-            for (int i = 0; i < nit; ++i) {
-                dmwf_status e = iterate_body(p, W, alpha, alpha, 0.0, cl, d, w, a, smap, first_pix,
-                                             W.mhi(), W.out2(), W.ctrl(), s);
-                if (e != DMWF_OK) return e;
-                first_pix = 0;
-            }
-            DMWF_HIP(hipMemcpyAsync(&p->h_ctrl[slot], W.ctrl(), sizeof(DevCtrl),
-                                    hipMemcpyDeviceToHost, s));
-            DMWF_HIP(hipEventRecord(p->batch_ev[slot], s));
-            return DMWF_OK;
-        };
-        // never more iterations than the cap allows, nor (replaying) than the
-        // replayed counts add up to: a replayed solve enqueues exactly its
-        // iterations
-        long long budget = sc->max_iter;
-        if (sc->replay_iters) {
-            long long sum = 0;
-            for (int k = 0; k < nl; ++k) sum += std::max(1, sc->replay_iters[k]);
-            budget = std::min(budget, sum);
+        st = launch_leg_syn(p, W.ap(0), W.spec(0), LegMaps{nm, W.ell_full(), 0, nullptr},
+                            p->syn_mb, s);
+        if (st != DMWF_OK) return st;
+        RingIO io{};
+        io.map_out = map_all;
+        io.pix_map = p->npix;
+        st = launch_ring(p, RING_SYN, W.spec(0), full, io, s);
+        if (st != DMWF_OK) return st;
+        io = RingIO{};
+        io.map_in = map_all;
+        io.d = d_all;
+        io.w = ninv_all;
+        io.ctrl = W.ctrl(0);
+        io.pix_map = p->npix;
+        st = launch_ring(p, RING_ANA_CRES, W.spec(0), full, io, s);
+        if (st != DMWF_OK) return st;
+    } else {
+        {
+            ProfScope ps(p, s, PROF_MISC);
+            hipLaunchKernelGGL(k_zero2, dim3(256), dim3(256), 0, s, a, (long long)nm * p->nalm);
         }
-        long long launched = 0;
-        int batch = 4, cur = 0;
-        int nb = (int)std::min<long long>(batch, budget);
-        st = enqueue(nb, cur);
+        RingIO io{};
+        io.d = d_all;
+        io.w = ninv_all;
+        io.pix_map = p->npix;
+        st = launch_ring(p, RING_ANA_FIRST, W.spec(0), full, io, s);
+        if (st != DMWF_OK) return st;
+        first_pix = 1;
+    }
+    DMWF_HIP(hipGetLastError());
+
+    // After every iteration k_control takes each map's decision.  The host
+    // enqueues iterations in growing batches with two batches in flight and
+    // reads the control blocks once per batch, so the GPU never waits for the
+    // host; iterations enqueued after a map's stop do nothing for that map.
+    auto enqueue = [&](int nit, int slot) -> dmwf_status {
+        for (int i = 0; i < nit; ++i) {
+            dmwf_status e = iterate_body(p, W, nm, 0.0, 0.0, 0.0, cl_all, d_all, ninv_all, a,
+                                         map_all, first_pix, nullptr, nullptr, W.ctrl(0), s);
+            if (e != DMWF_OK) return e;
+            first_pix = 0;
+        }
+        DMWF_HIP(hipMemcpyAsync(p->h_ctrl + (size_t)slot * nm, W.ctrl(0), nm * sizeof(DevCtrl),
+                                hipMemcpyDeviceToHost, s));
+        DMWF_HIP(hipEventRecord(p->batch_ev[slot], s));
+        return DMWF_OK;
+    };
+    auto all_done = [&](int slot) {
+        for (int k = 0; k < nm; ++k)
+            if (!p->h_ctrl[(size_t)slot * nm + k].done) return false;
+        return true;
+    };
+    // never more iterations than the cap allows, nor (replaying) than the
+    // replayed counts add up to: a replayed solve enqueues exactly its
+    // iterations
+    long long budget = sc->max_iter;
+    if (sc->replay_iters) {
+        long long sum = 0;
+        for (int i = 0; i < sc->n_replay; ++i) sum += std::max(1, sc->replay_iters[i]);
+        budget = std::min(budget, sum);
+    }
+    long long launched = 0;
+    int batch = 4, cur = 0;
+    int nb = (int)std::min<long long>(batch, budget);
+    st = enqueue(nb, cur);
+    if (st != DMWF_OK) return st;
+    launched += nb;
+    while (true) {
+        batch = std::min(2 * batch, 64);
+        nb = (int)std::min<long long>(batch, budget - launched);
+        st = enqueue(nb, cur ^ 1);
         if (st != DMWF_OK) return st;
         launched += nb;
-        DevCtrl fin{};
-        while (true) {
-            batch = std::min(2 * batch, 64);
-            nb = (int)std::min<long long>(batch, budget - launched);
-            st = enqueue(nb, cur ^ 1);
-            if (st != DMWF_OK) return st;
-            launched += nb;
-            DMWF_HIP(hipEventSynchronize(p->batch_ev[cur]));
-            if (p->h_ctrl[cur].done) {
-                DMWF_HIP(hipEventSynchronize(p->batch_ev[cur ^ 1]));
-                fin = p->h_ctrl[cur ^ 1];
-                break;
-            }
+        DMWF_HIP(hipEventSynchronize(p->batch_ev[cur]));
+        if (all_done(cur)) {
+            DMWF_HIP(hipEventSynchronize(p->batch_ev[cur ^ 1]));
             cur ^= 1;
+            break;
         }
-        std::vector<int> its(nl, 0);
-        DMWF_HIP(hipMemcpy(its.data(), W.lev_iters(), nl * sizeof(int), hipMemcpyDeviceToHost));
-        if (fin.status == 2) {
-            set_error("Cauchy ratio is NaN");
+        cur ^= 1;
+    }
+    const DevCtrl* fin = p->h_ctrl + (size_t)cur * nm;
+    dmwf_status result = DMWF_OK;
+    for (int k = 0; k < nm; ++k) {
+        if (fin[k].status == 2) {
+            set_error("Cauchy ratio of map " + std::to_string(k) + " is NaN");
             return DMWF_ERR_NONFINITE;
         }
-        const int nlev = fin.level + 1, total = fin.total;
-        const double ratio = fin.ratio;
-        const bool capped = fin.status == 1;
-        if (stats) {
-            for (int k = 0; k < nlev && k < stats->cap_levels; ++k) {
-                if (stats->iters_per_level) stats->iters_per_level[k] = its[k];
-                if (stats->xi_per_level) stats->xi_per_level[k] = lv[k].xi;
-                if (stats->lmax_per_level) stats->lmax_per_level[k] = lv[k].ell;
+        if (fin[k].status == 1) result = DMWF_ERR_NOT_CONVERGED;
+    }
+    if (stats) {
+        for (int k = 0; k < nm; ++k) {
+            dmwf_stats& S = stats[k];
+            const int nlev = fin[k].level + 1;
+            std::vector<int> its(lv[k].size(), 0);
+            DMWF_HIP(hipMemcpy(its.data(), W.lev_iters(k), its.size() * sizeof(int),
+                               hipMemcpyDeviceToHost));
+            for (int i = 0; i < nlev && i < S.cap_levels; ++i) {
+                if (S.iters_per_level) S.iters_per_level[i] = its[i];
+                if (S.xi_per_level) S.xi_per_level[i] = lv[k][i].xi;
+                if (S.lmax_per_level) S.lmax_per_level[i] = lv[k][i].ell;
+            }
+            S.n_levels = nlev;
+            S.n_iter = fin[k].total;
+            S.alpha = alpha[k];
+            S.final_cauchy = fin[k].ratio;
+            S.wf_residual = -1.0;
+            if (sc->want_residual) {
+                double res = 0.0;
+                st = residual_map(p, W, cl_all + (size_t)k * (L + 1), d_all + (size_t)k * p->npix,
+                                  ninv_all + (size_t)k * p->npix, a + (size_t)k * p->nalm, &res, s);
+                if (st != DMWF_OK) return st;
+                S.wf_residual = res;
             }
         }
-        if (stats) {
-            stats->n_levels = nlev;
-            stats->n_iter = total;
-            stats->alpha = alpha;
-            stats->final_cauchy = ratio;
-            stats->wf_residual = -1.0;
-        }
-        if (sc->want_residual && stats) {
-            double res = 0.0;
-            st = residual_map(p, W, cl, d, w, a, &res, s);
-            if (st != DMWF_OK) return st;
-            stats->wf_residual = res;
-        }
-        if (capped) result = DMWF_ERR_NOT_CONVERGED;
     }
     return result;
 }

@@ -83,25 +83,44 @@ struct DevCtrl {
     int status;  // 0 converged, 1 iteration cap reached, 2 NaN Cauchy ratio
     int level, it_level, total, nlev, max_iter, replay;
     double xi, mu, xi_over_sigma, ratio;
+    double alpha;  // min N over unmasked pixels of this map
+    double pad;
 };
 // Most cooling levels one solve may have (the per-level m-bound table is
 // kMaxLevels x ring pairs ints of workspace).
 constexpr int kMaxLevels = 1024;
 
-// Workspace layout (byte offsets from the workspace base).
+// Workspace layout (byte offsets from the workspace base).  The per-map
+// regions hold one slice per map of the plan, map k at offset + k * stride.
 struct WsLayout {
-    size_t spec;    // complex [nq][lp][2]: ring Fourier coefficients F_m / G_m, ring-major
-    size_t part;    // complex [nchunk_ana][n_alm + pad]: analysis partial sums
-    size_t ap;      // complex [n_alm + pad]: g-scaled a_lm for the synthesis
-    size_t aux;     // complex [n_alm + pad]: second a_lm-sized buffer
-    size_t cpart;   // double  [nq][2]: Cauchy partial sums per ring pair
-    size_t mhi;     // int     [nq]: per ring pair, the largest m carried at the current l_iter
-    size_t scal;    // small scalars: ints and doubles
-    size_t ctrl;    // DevCtrl
-    size_t levels;  // DevLevel [kMaxLevels]
-    size_t lev_iters;  // int [kMaxLevels]: iterations run per level
-    size_t mhi_tab;    // int [kMaxLevels][nq]: m bound of every ring pair per level
+    size_t spec;       // complex [nq][lp][2] per map: ring Fourier coefficients F_m / G_m
+    size_t part;       // complex [nchunk_ana][n_alm + pad] per map: analysis partial sums
+    size_t ap;         // complex [n_alm + pad] per map: g-scaled a_lm for the synthesis
+    size_t aux;        // complex [n_alm + pad] per map: second a_lm-sized buffer
+    size_t cpart;      // double  [nmaps][nq][2]: Cauchy partial sums per ring pair
+    size_t mhi;        // int     [nmaps][nq]: per ring pair, the largest m carried at l_iter
+    size_t ells;       // int     [3][nmaps]: l_iter, analysis band, input flags per map
+    size_t mdbl;       // double  [nmaps][4]: Cauchy sums (2), max N^-1, spare
+    size_t bmax;       // double  [nmaps][kCheckBlocks]: block maxima of N^-1
+    size_t scal;       // shared scalars: a band-limit int, residual block sums
+    size_t ctrl;       // DevCtrl [nmaps]
+    size_t levels;     // DevLevel [nmaps][kMaxLevels]
+    size_t lev_iters;  // int [nmaps][kMaxLevels]: iterations run per level
+    size_t mhi_tab;    // int [nmaps][kMaxLevels][nq]: m bound of every ring pair per level
     size_t total;
+    // per-map strides in elements of each region's type
+    long long spec_map, part_map, alm_map;
+};
+
+// Blocks of the per-map input screening reduction.
+constexpr int kCheckBlocks = 1024;
+
+// The maps of one Legendre launch.
+struct LegMaps {
+    int nm;               // maps in the launch
+    const int* ell;       // band limit of map k at ell[k * ell_stride] (device)
+    int ell_stride;       // 0: one band limit for every map
+    const DevCtrl* ctrl;  // per-map control blocks, or NULL; a stopped map is skipped
 };
 
 }  // namespace dmwf
@@ -110,6 +129,9 @@ struct dmwf_plan {
     int nside, lmax, nmaps, nq, nrings, device;
     long long npix, nalm;
     int nchunk_ana, nchunk_syn;
+    // maps per wave of the Legendre kernels (1, 2 or 4): the recurrence is
+    // computed once for all of them; set by dmwf_autotune or by default
+    int syn_mb = 1, ana_mb = 1;
     int lp;        // m-row length of the ring-major F/G buffer, lmax+1 rounded up to 4
     double omega;  // 4 pi / Npix
     // device tables
@@ -208,11 +230,12 @@ __host__ __device__ inline long long alm_base(int m, int lmax) {
 
 // ---- launchers (ring.hip, legendre.hip, api.hip) ----
 dmwf_status launch_seeds(dmwf_plan* p, hipStream_t s);
-// done (may be NULL): device flag; the kernels return at once when it is set.
-dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const int* ell_dev,
-                           const int* done, hipStream_t s);
-dmwf_status launch_leg_ana(dmwf_plan* p, const double2* spec, double2* part, const int* ell_dev,
-                           const int* done, hipStream_t s);
+// Legendre stages over the maps of lm.  ap, spec and part point at map 0's
+// slice; the per-map strides are the workspace's.
+dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const LegMaps& lm,
+                           int mb, hipStream_t s);
+dmwf_status launch_leg_ana(dmwf_plan* p, const double2* spec, double2* part, const LegMaps& lm,
+                           int mb, hipStream_t s);
 
 // Ring stage modes.  SYN: F -> map.  ANA*: a pixel map -> G, the map being
 // map_in (ANA), d on unmasked pixels (ANA_FIRST), w (d - map_in) (ANA_RESID),
@@ -235,20 +258,32 @@ struct RingIO {
     const double* d;        // data
     const double* w;        // N^-1
     double* s_map;          // RING_ITER: s_prev in, s out
-    double* cpart;          // RING_ITER: Cauchy partials [nq][2]
-    double xi, alpha;       // RING_ITER: pixel step coefficients
+    double* cpart;          // RING_ITER: Cauchy partials [maps][nq][2]
+    double xi, alpha;       // pixel step coefficients when ctrl is NULL
     int first;              // RING_ITER: s_prev taken as 0
-    // RING_ITER inside the solve loop: xi and the m bounds of the current and
-    // next level come from the device control block; nothing runs once done
+    // Per-map control blocks or NULL.  RING_ITER inside the solve loop takes
+    // xi, alpha and the m bounds of the current and next level from them, and
+    // nothing runs for a map whose solve has stopped; RING_ANA_CRES takes
+    // xi = alpha of each map.
     const DevCtrl* ctrl;
-    const int* mhi_tab;
+    const int* mhi_tab;     // [maps][kMaxLevels][nq]
+    long long pix_map;      // doubles between consecutive maps' pixel arrays
 };
-// ell_syn bounds the m of F used by the synthesis, ell_ana the m of G written
-// by the analysis (device scalars); mhi_syn / mhi_ana are the per-ring-pair
-// bounds for the same band limits (beyond them every lambda_lm is skipped, so
-// F is zero and G is never read).
-dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const int* ell_syn,
-                        const int* ell_ana, const int* mhi_syn, const int* mhi_ana,
+// The maps of one ring launch (grid.y).  ell_syn bounds the m of F used by
+// the synthesis, ell_ana the m of G written by the analysis (device ints, map
+// k at k * ell_stride); mhi_syn / mhi_ana are the per-ring-pair bounds for the
+// same band limits (map k at k * mhi_stride; beyond them every lambda_lm is
+// skipped, so F is zero and G is never read).
+struct RingMaps {
+    int nm;
+    const int* ell_syn;
+    const int* ell_ana;
+    int ell_stride;
+    const int* mhi_syn;
+    const int* mhi_ana;
+    int mhi_stride;
+};
+dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const RingMaps& rm,
                         const RingIO& io, hipStream_t s);
 // mhi[q] = largest m <= *ell_dev whose recurrence start is <= *ell_dev (-1 if none).
 dmwf_status launch_mhi(dmwf_plan* p, const int* ell_dev, int* mhi, hipStream_t s);

@@ -176,11 +176,14 @@ struct SynArgs {
     const double* s0;
     const double* s1;
     const double* A;
-    const double2* ap;
-    double2* spec;
-    const int* ell;
-    int lmax, nq, lp;
-    const int* done;
+    const double2* ap;       // pre-scaled a_lm of map 0; map k at ap + k * ap_map
+    long long ap_map;
+    double2* spec;           // F rows of map 0; map k at spec + k * spec_map
+    long long spec_map;
+    const int* ell;          // band limit of map k at ell[k * ell_stride]
+    int ell_stride;
+    const DevCtrl* ctrl;     // per-map control blocks (solve loop) or NULL
+    int lmax, nq, lp, nm;
 };
 
 // The analysis takes its coefficient row through LDS, kChunk l at a time per
@@ -201,24 +204,36 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // One even/odd pair of recurrence steps (l even offset from m, l+1 odd) for
-// the K rings of a lane.
-template <int K>
+// the K rings of a lane, contracted with the coefficients of MB maps: the
+// recurrence is shared, only the FMAs of the sums are per map.
+template <int K, int MB>
 __device__ __forceinline__ void syn_pair(int l, bool odd_live, const double* __restrict__ A,
-                                         const double2* __restrict__ ap, const double (&x)[K],
-                                         double (&p1)[K], double (&p2)[K], double (&er)[K],
-                                         double (&ei)[K], double (&orr)[K], double (&oi)[K]) {
+                                         const double2* const (&ap)[MB], const double (&x)[K],
+                                         double (&p1)[K], double (&p2)[K], double (&er)[MB][K],
+                                         double (&ei)[MB][K], double (&orr)[MB][K],
+                                         double (&oi)[MB][K]) {
     const double Ae = A[l], Ao = A[l + 1];
-    const double2 ce = ap[l];
-    double2 co = ap[l + 1];
-    if (!odd_live) co = make_double2(0.0, 0.0);
+    double2 ce[MB], co[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        ce[i] = ap[i][l];
+        co[i] = ap[i][l + 1];
+        if (!odd_live) co[i] = make_double2(0.0, 0.0);
+    }
 #pragma unroll
     for (int t = 0; t < K; ++t) {
         const double ue = fma(Ae * x[t], p1[t], -p2[t]);
-        er[t] = fma(ue, ce.x, er[t]);
-        ei[t] = fma(ue, ce.y, ei[t]);
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            er[i][t] = fma(ue, ce[i].x, er[i][t]);
+            ei[i][t] = fma(ue, ce[i].y, ei[i][t]);
+        }
         const double uo = fma(Ao * x[t], ue, -p1[t]);
-        orr[t] = fma(uo, co.x, orr[t]);
-        oi[t] = fma(uo, co.y, oi[t]);
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            orr[i][t] = fma(uo, co[i].x, orr[i][t]);
+            oi[i][t] = fma(uo, co[i].y, oi[i][t]);
+        }
         p2[t] = ue;
         p1[t] = uo;
     }
@@ -237,26 +252,46 @@ __device__ __forceinline__ void inject(int l, const int (&ls)[K], const double (
         }
 }
 
-template <int K>
+// Band limits of the MB maps of this workgroup's map group: -1 for a map past
+// the end of the batch or whose solve has stopped.  Returns their maximum.
+template <int MB>
+__device__ __forceinline__ int group_ells(int mg, int nm, const int* ell, int ell_stride,
+                                          const DevCtrl* ctrl, int (&ellm)[MB]) {
+    int e = -1;
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        const int k = mg + i;
+        int v = -1;
+        if (k < nm && !(ctrl && ctrl[k].done)) v = ell[k * ell_stride];
+        ellm[i] = v;
+        e = max(e, v);
+    }
+    return e;
+}
+
+template <int K, int MB>
 __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn(SynArgs a) {
     // The waves of a workgroup take consecutive m of the same ring chunk; their
     // results meet in LDS and leave as whole segments of the ring-major rows
-    // of F.
+    // of F, one map after the other.
     __shared__ double2 stage[K][64][kLegWaves][2];
-    if (a.done && *a.done) return;
+    const int mg = blockIdx.y * MB;
+    int ellm[MB];
+    const int ell = group_ells<MB>(mg, a.nm, a.ell, a.ell_stride, a.ctrl, ellm);
+    if (ell < 0) return;
     const int w = threadIdx.x >> 6;
     // wave-uniform; readfirstlane lets the compiler use scalar loads for the
     // per-(l, m) coefficients
     const LegTile tile = leg_tile((a.nq + 64 * K - 1) / (64 * K));
     const int m = __builtin_amdgcn_readfirstlane(tile.group * kLegWaves + w);
-    const int ell = *a.ell;
     if (tile.group * kLegWaves > ell) return;  // whole workgroup above the band limit
     const bool live = m <= ell;
     const int lane = threadIdx.x & 63;
     const int nq = a.nq;
     const int q0 = tile.chunk * (64 * K) + lane;
     const size_t mo = (size_t)m * nq;
-    double x[K], p1[K], p2[K], er[K], ei[K], orr[K], oi[K], s0[K], s1[K];
+    double x[K], p1[K], p2[K], s0[K], s1[K];
+    double er[MB][K], ei[MB][K], orr[MB][K], oi[MB][K];
     int ls[K];
     int lo = kNever, hi = -1;
     // all loads first, from clamped (valid) addresses, then the masks: one
@@ -279,7 +314,9 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn(SynArgs a) {
         if (!act) s0[t] = s1[t] = 0.0;
         lo = min(lo, l0);
         if (act) hi = max(hi, l0);
-        p1[t] = p2[t] = er[t] = ei[t] = orr[t] = oi[t] = 0.0;
+        p1[t] = p2[t] = 0.0;
+#pragma unroll
+        for (int i = 0; i < MB; ++i) er[i][t] = ei[i][t] = orr[i][t] = oi[i][t] = 0.0;
     }
     // uniform across the wave after the reduction; say so, so that the
     // loop bounds below live in scalar registers
@@ -288,34 +325,47 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn(SynArgs a) {
     if (lo <= ell) {
         const long long base = alm_base(m, a.lmax);
         const double* A = a.A + base;
-        const double2* ap = a.ap + base;
+        // maps past the end of the batch read the last map's row; their sums
+        // are not stored.  A map whose band limit is below the group's reads
+        // zeros beyond it (the harmonic step stores them).
+        const double2* ap[MB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+            ap[i] = a.ap + (long long)min(mg + i, a.nm - 1) * a.ap_map + base;
         // every start is the first l of a 16-l block counted from m
         int l = lo;
         for (; l + kLegB - 1 <= ell; l += kLegB) {
             if (l <= hi) inject<K>(l, ls, s0, s1, p1, p2);
 #pragma unroll
             for (int j = 0; j < kLegB / 2; ++j)
-                syn_pair<K>(l + 2 * j, true, A, ap, x, p1, p2, er, ei, orr, oi);
+                syn_pair<K, MB>(l + 2 * j, true, A, ap, x, p1, p2, er, ei, orr, oi);
         }
         if (l <= ell) {
             if (l <= hi) inject<K>(l, ls, s0, s1, p1, p2);
-            for (; l <= ell; l += 2) syn_pair<K>(l, l + 1 <= ell, A, ap, x, p1, p2, er, ei, orr, oi);
+            for (; l <= ell; l += 2)
+                syn_pair<K, MB>(l, l + 1 <= ell, A, ap, x, p1, p2, er, ei, orr, oi);
         }
     }
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-        stage[t][lane][w][0] = make_double2(er[t] + orr[t], ei[t] + oi[t]);
-        stage[t][lane][w][1] = make_double2(er[t] - orr[t], ei[t] - oi[t]);
-    }
-    __syncthreads();
     constexpr int kSlots = kLegWaves * 2;
     const int m0 = tile.group * kLegWaves;
-    for (int idx = threadIdx.x; idx < K * 64 * kSlots; idx += 64 * kLegWaves) {
-        const int slot = idx % kSlots, rr = idx / kSlots;
-        const int q = tile.chunk * (64 * K) + rr;
-        const int mm = m0 + (slot >> 1);
-        if (q < nq && mm <= ell)
-            a.spec[((size_t)q * a.lp + mm) * 2 + (slot & 1)] = stage[rr >> 6][rr & 63][slot >> 1][slot & 1];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        if (i > 0) __syncthreads();  // the previous map's rows have left the stage
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            stage[t][lane][w][0] = make_double2(er[i][t] + orr[i][t], ei[i][t] + oi[i][t]);
+            stage[t][lane][w][1] = make_double2(er[i][t] - orr[i][t], ei[i][t] - oi[i][t]);
+        }
+        __syncthreads();
+        const int ei_ = ellm[i];
+        double2* spec = a.spec + (long long)(mg + i) * a.spec_map;
+        for (int idx = threadIdx.x; idx < K * 64 * kSlots; idx += 64 * kLegWaves) {
+            const int slot = idx % kSlots, rr = idx / kSlots;
+            const int q = tile.chunk * (64 * K) + rr;
+            const int mm = m0 + (slot >> 1);
+            if (q < nq && mm <= ei_)
+                spec[((size_t)q * a.lp + mm) * 2 + (slot & 1)] = stage[rr >> 6][rr & 63][slot >> 1][slot & 1];
+        }
     }
 }
 
@@ -328,12 +378,15 @@ struct AnaArgs {
     const double* s0;
     const double* s1;
     const double* A;
-    const double2* spec;
-    double2* part;
-    size_t part_stride;
-    const int* ell;
-    int lmax, nq, lp;
-    const int* done;
+    const double2* spec;     // G rows of map 0; map k at spec + k * spec_map
+    long long spec_map;
+    double2* part;           // partial sums of map 0, chunk c at part + c * part_stride;
+    size_t part_stride;      // map k at part + k * part_map
+    long long part_map;
+    const int* ell;          // band limit of map k at ell[k * ell_stride]
+    int ell_stride;
+    const DevCtrl* ctrl;     // per-map control blocks (solve loop) or NULL
+    int lmax, nq, lp, nm;
 };
 
 // Cross-lane sums through the lane-swap instructions (no LDS).  xsum32(a, b):
@@ -361,78 +414,92 @@ __device__ __forceinline__ double xsum_rows(double v) {
 // rows are 8 banks apart (66 double2 = 264 dwords).
 constexpr int kRedRow = 66;
 
-// Eight even/odd pairs (16 l) of the lane's K rings, A_l staged at CA[i0..].
-// Pair j leaves through
-// red[j][.]: lanes 0..31 hold the even l0 + 2j summed over lanes i and i+32,
-// lanes 32..63 the odd l0 + 2j + 1.
+// Eight even/odd pairs (16 l) of the lane's K rings for MB maps, A_l staged
+// at CA[i0..].  Pair j of map i leaves through red[j][i][.]: lanes 0..31 hold
+// the even l0 + 2j summed over lanes i and i+32, lanes 32..63 the odd
+// l0 + 2j + 1.
 // Slots t < T0 hold rings that have not started yet (all their starts lie
 // beyond this block): their terms are zero and their state stays (0, 0), so
 // they are skipped.
-template <int K, int T0>
+template <int K, int MB, int T0>
 __device__ __forceinline__ void ana_block(const double* CA, int i0,
                                           const double (&x)[K], double (&p1)[K], double (&p2)[K],
-                                          const double (&gpr)[K], const double (&gpi)[K],
-                                          const double (&gmr)[K], const double (&gmi)[K],
-                                          double2 (*red)[kRedRow], int lane) {
+                                          const double (&gpr)[MB][K], const double (&gpi)[MB][K],
+                                          const double (&gmr)[MB][K], const double (&gmi)[MB][K],
+                                          double2 (*red)[MB][kRedRow], int lane) {
 #pragma unroll
     for (int j = 0; j < kLegB / 2; ++j) {
         const double2 AA = *reinterpret_cast<const double2*>(CA + i0 + 2 * j);
         const double Ae = AA.x, Ao = AA.y;
-        double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;
+        double er[MB], ei[MB], orr[MB], oi[MB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) er[i] = ei[i] = orr[i] = oi[i] = 0.0;
 #pragma unroll
         for (int t = T0; t < K; ++t) {
             const double ue = fma(Ae * x[t], p1[t], -p2[t]);
-            er = fma(ue, gpr[t], er);
-            ei = fma(ue, gpi[t], ei);
+#pragma unroll
+            for (int i = 0; i < MB; ++i) {
+                er[i] = fma(ue, gpr[i][t], er[i]);
+                ei[i] = fma(ue, gpi[i][t], ei[i]);
+            }
             const double uo = fma(Ao * x[t], ue, -p1[t]);
-            orr = fma(uo, gmr[t], orr);
-            oi = fma(uo, gmi[t], oi);
+#pragma unroll
+            for (int i = 0; i < MB; ++i) {
+                orr[i] = fma(uo, gmr[i][t], orr[i]);
+                oi[i] = fma(uo, gmi[i][t], oi[i]);
+            }
             p2[t] = ue;
             p1[t] = uo;
         }
-        red[j][lane + (lane >> 5)] = make_double2(xsum32(er, orr), xsum32(ei, oi));
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+            red[j][i][lane + (lane >> 5)] = make_double2(xsum32(er[i], orr[i]), xsum32(ei[i], oi[i]));
     }
 }
 
 // ana_block over the slots t0..K-1, t0 wave-uniform.
-template <int K, int T = 0>
+template <int K, int MB, int T = 0>
 __device__ __forceinline__ void ana_block_from(int t0, const double* CA, int i0,
                                                const double (&x)[K], double (&p1)[K],
-                                               double (&p2)[K], const double (&gpr)[K],
-                                               const double (&gpi)[K], const double (&gmr)[K],
-                                               const double (&gmi)[K], double2 (*red)[kRedRow],
-                                               int lane) {
+                                               double (&p2)[K], const double (&gpr)[MB][K],
+                                               const double (&gpi)[MB][K],
+                                               const double (&gmr)[MB][K],
+                                               const double (&gmi)[MB][K],
+                                               double2 (*red)[MB][kRedRow], int lane) {
     if constexpr (T < K - 1) {
         if (t0 > T) {
-            ana_block_from<K, T + 1>(t0, CA, i0, x, p1, p2, gpr, gpi, gmr, gmi, red, lane);
+            ana_block_from<K, MB, T + 1>(t0, CA, i0, x, p1, p2, gpr, gpi, gmr, gmi, red, lane);
             return;
         }
     }
-    ana_block<K, T>(CA, i0, x, p1, p2, gpr, gpi, gmr, gmi, red, lane);
+    ana_block<K, MB, T>(CA, i0, x, p1, p2, gpr, gpi, gmr, gmi, red, lane);
 }
 
-template <int K>
+template <int K, int MB>
 __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
-    __shared__ double2 red_all[kLegWaves][kLegB / 2][kRedRow];
+    __shared__ double2 red_all[kLegWaves][kLegB / 2][MB][kRedRow];
     __shared__ double coef[kLegWaves][2][kChunk];  // per wave: two chunks of A
-    if (a.done && *a.done) return;
+    const int mg = blockIdx.y * MB;
+    int ellm[MB];
+    const int ell = group_ells<MB>(mg, a.nm, a.ell, a.ell_stride, a.ctrl, ellm);
     const int w = threadIdx.x >> 6;
     const LegTile tile = leg_tile((a.nq + 64 * K - 1) / (64 * K));
     const int m = __builtin_amdgcn_readfirstlane(tile.group * kLegWaves + w);
-    const int ell = *a.ell;
     if (m > ell) return;
-    double2 (*red)[kRedRow] = red_all[w];
+    double2 (*red)[MB][kRedRow] = red_all[w];
     const int lane = threadIdx.x & 63;
     const int nq = a.nq;
     const int q0 = tile.chunk * (64 * K) + lane;
     const size_t mo = (size_t)m * nq;
-    double x[K], p1[K], p2[K], gpr[K], gpi[K], gmr[K], gmi[K], s0[K], s1[K];
+    double x[K], p1[K], p2[K], s0[K], s1[K];
+    double gpr[MB][K], gpi[MB][K], gmr[MB][K], gmi[MB][K];
     int ls[K];
     int lo = kNever, hi = -1;
     // all loads first, from clamped (valid) addresses, then the masks: one
-    // memory round trip for the whole prologue.  G of rings that the ring
-    // stage did not write (beyond their m bound) is loaded but never used.
-    double2 gn[K], gs[K];
+    // memory round trip for the whole prologue.  G of a map is used only for
+    // rings whose start lies within that map's band limit: the ring stage
+    // wrote it there, and may not have elsewhere.
+    double2 gn[MB][K], gs[MB][K];
 #pragma unroll
     for (int t = 0; t < K; ++t) {
         const int qc = min(q0 + 64 * t, nq - 1);
@@ -440,24 +507,29 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
         ls[t] = a.ls[mo + qc];
         s0[t] = a.s0[mo + qc];
         s1[t] = a.s1[mo + qc];
-        const double2* g = a.spec + ((size_t)qc * a.lp + m) * 2;
-        gn[t] = g[0];
-        gs[t] = g[1];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            const double2* g = a.spec + (long long)min(mg + i, a.nm - 1) * a.spec_map +
+                               ((size_t)qc * a.lp + m) * 2;
+            gn[i][t] = g[0];
+            gs[i][t] = g[1];
+        }
     }
 #pragma unroll
     for (int t = 0; t < K; ++t) {
-        int l0 = q0 + 64 * t < nq ? ls[t] : kNever;
-        if (l0 > ell) l0 = kNever;
+        const int lr = q0 + 64 * t < nq ? ls[t] : kNever;
+        const int l0 = lr > ell ? kNever : lr;
         ls[t] = l0;
         const bool act = l0 != kNever;
-        if (!act) {
-            s0[t] = s1[t] = 0.0;
-            gn[t] = gs[t] = make_double2(0.0, 0.0);
+        if (!act) s0[t] = s1[t] = 0.0;
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            if (!(act && lr <= ellm[i])) gn[i][t] = gs[i][t] = make_double2(0.0, 0.0);
+            gpr[i][t] = gn[i][t].x + gs[i][t].x;
+            gpi[i][t] = gn[i][t].y + gs[i][t].y;
+            gmr[i][t] = gn[i][t].x - gs[i][t].x;
+            gmi[i][t] = gn[i][t].y - gs[i][t].y;
         }
-        gpr[t] = gn[t].x + gs[t].x;
-        gpi[t] = gn[t].y + gs[t].y;
-        gmr[t] = gn[t].x - gs[t].x;
-        gmi[t] = gn[t].y - gs[t].y;
         lo = min(lo, l0);
         if (act) hi = max(hi, l0);
         p1[t] = p2[t] = 0.0;
@@ -470,15 +542,24 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
 #pragma unroll
     for (int t = 0; t < K; ++t) slot_lo[t] = __builtin_amdgcn_readfirstlane(wave_min(ls[t]));
     const long long base = alm_base(m, a.lmax);
-    double2* out = a.part + tile.chunk * a.part_stride + base;
+    double2* out[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+        out[i] = a.part + (long long)(mg + i) * a.part_map + tile.chunk * a.part_stride + base;
     if (lo > ell) {
-        for (int l = m + lane; l <= ell; l += 64) out[l] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+            if (ellm[i] >= 0)
+                for (int l = m + lane; l <= ell; l += 64) out[i][l] = make_double2(0.0, 0.0);
         return;
     }
     const double* A = a.A + base;
     // every start is the first l of a 16-l block counted from m
     const int L0 = lo;
-    for (int l = m + lane; l < L0; l += 64) out[l] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+        if (ellm[i] >= 0)
+            for (int l = m + lane; l < L0; l += 64) out[i][l] = make_double2(0.0, 0.0);
     // lane sums eight of the 32 half-sums of l0 + rb: row rb >> 1, half rb & 1,
     // part rp = lane >> 4; the four parts then combine across lanes 16 apart
     const int rb = lane & 15, rp = lane >> 4;
@@ -505,19 +586,25 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
 #pragma unroll
             for (int t = K - 1; t >= 0; --t)
                 if (slot_lo[t] <= l0) t0 = t;
-            ana_block_from<K>(t0, cf[cur], l0 - cb, x, p1, p2, gpr, gpi, gmr, gmi, red, lane);
+            ana_block_from<K, MB>(t0, cf[cur], l0 - cb, x, p1, p2, gpr, gpi, gmr, gmi, red, lane);
             wave_lds_sync();
-            double sr = 0.0, si = 0.0;
+            double sr[MB], si[MB];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const double2 v = red[rb >> 1][rcol + i];
-                sr += v.x;
-                si += v.y;
+            for (int i = 0; i < MB; ++i) {
+                sr[i] = si[i] = 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const double2 v = red[rb >> 1][i][rcol + u];
+                    sr[i] += v.x;
+                    si[i] += v.y;
+                }
             }
             wave_lds_sync();
-            sr = xsum_rows(sr);
-            si = xsum_rows(si);
-            if (rp == 0 && l0 + rb <= ell) out[l0 + rb] = make_double2(sr, si);
+#pragma unroll
+            for (int i = 0; i < MB; ++i) {
+                const double vr = xsum_rows(sr[i]), vi = xsum_rows(si[i]);
+                if (rp == 0 && l0 + rb <= ell && ellm[i] >= 0) out[i][l0 + rb] = make_double2(vr, vi);
+            }
         }
         cf[cur ^ 1][lane] = na;
         wave_lds_sync();
@@ -560,24 +647,51 @@ dmwf_status launch_mhi(dmwf_plan* p, const int* ell_dev, int* mhi, hipStream_t s
     return DMWF_OK;
 }
 
-dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const int* ell_dev,
-                           const int* done, hipStream_t s) {
-    SynArgs a{p->d_x, p->d_ls, p->d_s0, p->d_s1, p->d_A,  ap,
-              spec,   ell_dev, p->lmax, p->nq,   p->lp,   done};
+namespace {
+
+// Largest instantiated maps-per-wave count <= want and <= nm.
+int pick_mb(int want, int nm, int cap) {
+    int mb = 1;
+    while (mb * 2 <= want && mb * 2 <= nm && mb * 2 <= cap) mb *= 2;
+    return mb;
+}
+
+int leg_groups8(const dmwf_plan* p) {
+    // m-groups of kLegWaves consecutive m, rounded up to whole XCD rounds
+    return ((p->lmax + kLegWaves) / kLegWaves + 7) / 8 * 8;
+}
+
+}  // namespace
+
+dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const LegMaps& lm,
+                           int mb_want, hipStream_t s) {
+    SynArgs a{p->d_x,       p->d_ls,    p->d_s0,        p->d_s1,  p->d_A,
+              ap,           p->ws.alm_map, spec,        p->ws.spec_map,
+              lm.ell,       lm.ell_stride, lm.ctrl,     p->lmax,  p->nq,
+              p->lp,        lm.nm};
     ProfScope ps(p, s, PROF_LEG_SYN);
-    const int ng8 = ((p->lmax + kLegWaves) / kLegWaves + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_leg_syn<kSynK>, dim3(p->nchunk_syn * ng8), dim3(64 * kLegWaves), 0, s, a);
+    const int mb = pick_mb(mb_want, lm.nm, 4);
+    const dim3 grid(p->nchunk_syn * leg_groups8(p), (lm.nm + mb - 1) / mb);
+    const dim3 block(64 * kLegWaves);
+    switch (mb) {
+        case 4: hipLaunchKernelGGL((k_leg_syn<kSynK, 4>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_leg_syn<kSynK, 2>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_leg_syn<kSynK, 1>), grid, block, 0, s, a); break;
+    }
     DMWF_HIP(hipGetLastError());
     return DMWF_OK;
 }
 
-dmwf_status launch_leg_ana(dmwf_plan* p, const double2* spec, double2* part, const int* ell_dev,
-                           const int* done, hipStream_t s) {
-    AnaArgs a{p->d_x,  p->d_ls, p->d_s0, p->d_s1, p->d_A, spec, part,
-              (size_t)p->nalm + kTablePad, ell_dev, p->lmax, p->nq, p->lp, done};
+dmwf_status launch_leg_ana(dmwf_plan* p, const double2* spec, double2* part, const LegMaps& lm,
+                           int mb_want, hipStream_t s) {
+    (void)mb_want;
+    AnaArgs a{p->d_x,   p->d_ls,        p->d_s0,  p->d_s1, p->d_A,
+              spec,     p->ws.spec_map, part,     (size_t)p->nalm + kTablePad,
+              p->ws.part_map, lm.ell,   lm.ell_stride, lm.ctrl, p->lmax,
+              p->nq,    p->lp,          lm.nm};
     ProfScope ps(p, s, PROF_LEG_ANA);
-    const int ng8 = ((p->lmax + kLegWaves) / kLegWaves + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_leg_ana<kAnaK>, dim3(p->nchunk_ana * ng8), dim3(64 * kLegWaves), 0, s, a);
+    const dim3 grid(p->nchunk_ana * leg_groups8(p), lm.nm);
+    hipLaunchKernelGGL((k_leg_ana<kAnaK, 1>), grid, dim3(64 * kLegWaves), 0, s, a);
     DMWF_HIP(hipGetLastError());
     return DMWF_OK;
 }

@@ -41,15 +41,13 @@ enum PixSource { PIX_MAP = 0, PIX_FIRST = 1, PIX_WRES = 2, PIX_WD = 3, PIX_CRES 
 struct RingArgs {
     RingGeom g;
     int nq, lmax, lp;
-    const int* ell_syn;
-    const int* ell_ana;
     double2* spec;
+    long long spec_map;
     int mode;
     int pix;
     RingIO io;
+    RingMaps rm;
     const int* qlist;
-    const int* mhi_syn;
-    const int* mhi_ana;
     const int* Mq;
     const int* blue;
     const long long* coff;
@@ -322,8 +320,17 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     extern __shared__ double2 buf[];
     __shared__ double2 red[NT / 64];
     __shared__ double2 tw[128];
-    const DevCtrl* ctrl = a.io.ctrl;
+    // grid.y is the map: every per-map array is offset to its slice here
+    const int map = blockIdx.y;
+    const DevCtrl* ctrl = a.io.ctrl ? a.io.ctrl + map : nullptr;
     if (ctrl && ctrl->done) return;
+    const long long po = map * a.io.pix_map;
+    const double* dd = a.io.d + po;
+    const double* ww = a.io.w + po;
+    const double* min_ = a.io.map_in + po;
+    double* mout = a.io.map_out + po;
+    double* smap = a.io.s_map + po;
+    double2* spec = a.spec + map * a.spec_map;
     const int q = a.qlist[blockIdx.x];
     const int n = a.g.nph[q];
     const int M = a.Mq[q];
@@ -335,17 +342,21 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     const bool eq = (q == a.nq - 1);
     const long long st0 = a.g.start_n[q], st1 = a.g.start_s[q];
     int msyn, mana;
-    if (ctrl) {
+    if (ctrl && a.mode == RING_ITER) {
         // m bounds of the current level (synthesis) and of the next (analysis)
+        const int* tab = a.io.mhi_tab + (size_t)map * kMaxLevels * a.nq;
         const int lev = ctrl->level, nxt = min(lev + 1, ctrl->nlev - 1);
-        msyn = a.io.mhi_tab[(size_t)lev * a.nq + q];
-        mana = a.io.mhi_tab[(size_t)nxt * a.nq + q];
+        msyn = tab[(size_t)lev * a.nq + q];
+        mana = tab[(size_t)nxt * a.nq + q];
     } else {
-        msyn = a.mhi_syn[q];
-        mana = a.mhi_ana[q];
+        msyn = a.rm.mhi_syn[map * a.rm.mhi_stride + q];
+        mana = a.rm.mhi_ana[map * a.rm.mhi_stride + q];
     }
-    const int ell = min(*a.ell_syn, msyn);
-    const int ella = min(*a.ell_ana, mana);
+    const int ell = min(a.rm.ell_syn[map * a.rm.ell_stride], msyn);
+    const int ella = min(a.rm.ell_ana[map * a.rm.ell_stride], mana);
+    // pixel step coefficients: the map's own in the solve loop
+    const double xi_ = ctrl ? (a.pix == PIX_CRES ? ctrl->alpha : ctrl->xi) : a.io.xi;
+    const double alpha_ = ctrl ? ctrl->alpha : a.io.alpha;
     const int tid = threadIdx.x;
     double rn[J], rs[J];
     // m per thread and batch in the fold and unfold
@@ -358,7 +369,7 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
         // Z_k = H^N_k + i H^S_k, H_k = sum over m = k mod n of F_m e^{i m phi0}
         // with F_{-m} = conj(F_m).  The row of F is read once, coalesced, and
         // scattered: m feeds bin m mod n, and -m feeds bin -m mod n.
-        const double2* Fq = a.spec + (size_t)q * a.lp * 2;
+        const double2* Fq = spec + (size_t)q * a.lp * 2;
         // Bins collide when 2 ell > n; at 2 ell = n only m = n/2 meets -m,
         // which one thread handles alone.
         const bool alias = 2 * ell > n;
@@ -448,16 +459,16 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
                 const long long p = (h == 0 ? st0 : st1) + j;
                 double v;
                 switch (a.pix) {
-                    case PIX_FIRST: v = a.io.w[p] > 0.0 ? a.io.d[p] : 0.0; break;
-                    case PIX_WRES: v = a.io.w[p] * (a.io.d[p] - a.io.map_in[p]); break;
-                    case PIX_WD: v = a.io.w[p] * a.io.d[p]; break;
+                    case PIX_FIRST: v = ww[p] > 0.0 ? dd[p] : 0.0; break;
+                    case PIX_WRES: v = ww[p] * (dd[p] - min_[p]); break;
+                    case PIX_WD: v = ww[p] * dd[p]; break;
                     case PIX_CRES: {
-                        const double w = a.io.w[p];
-                        const double cc = a.io.xi * w / fma(a.io.xi - a.io.alpha, w, 1.0);
-                        v = cc * (a.io.d[p] - a.io.map_in[p]);
+                        const double w = ww[p];
+                        const double cc = xi_ * w / fma(xi_ - alpha_, w, 1.0);
+                        v = cc * (dd[p] - min_[p]);
                         break;
                     }
-                    default: v = a.io.map_in[p]; break;
+                    default: v = min_[p]; break;
                 }
                 if (h == 0) rn[t] = v;
                 else rs[t] = v;
@@ -497,15 +508,15 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
                     yN[u] = y.x;
                     yS[u] = y.y;
                     if (a.mode != RING_SYN) {
-                        dN[u] = a.io.d[st0 + j];
-                        wN[u] = a.io.w[st0 + j];
+                        dN[u] = dd[st0 + j];
+                        wN[u] = ww[st0 + j];
                         if (!eq) {
-                            dS[u] = a.io.d[st1 + j];
-                            wS[u] = a.io.w[st1 + j];
+                            dS[u] = dd[st1 + j];
+                            wS[u] = ww[st1 + j];
                         }
                         if (a.mode == RING_ITER && !a.io.first) {
-                            pN[u] = a.io.s_map[st0 + j];
-                            if (!eq) pS[u] = a.io.s_map[st1 + j];
+                            pN[u] = smap[st0 + j];
+                            if (!eq) pS[u] = smap[st1 + j];
                         }
                     }
                 }
@@ -518,23 +529,23 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
                 rs[t] = 0.0;
                 if (j >= n) continue;
                 if (a.mode == RING_SYN) {
-                    a.io.map_out[st0 + j] = yN[u];
-                    if (!eq) a.io.map_out[st1 + j] = yS[u];
+                    mout[st0 + j] = yN[u];
+                    if (!eq) mout[st1 + j] = yS[u];
                 } else if (a.mode == RING_SYN_WRES) {
                     rn[t] = wN[u] * (dN[u] - yN[u]);
                     rs[t] = eq ? 0.0 : wS[u] * (dS[u] - yS[u]);
                 } else {
-                    const double xi = ctrl ? ctrl->xi : a.io.xi, xa = xi - a.io.alpha;
+                    const double xi = xi_, xa = xi_ - alpha_;
                     double ds = yN[u] - pN[u];
                     num = fma(ds, ds, num);
                     den = fma(yN[u], yN[u], den);
-                    a.io.s_map[st0 + j] = yN[u];
+                    smap[st0 + j] = yN[u];
                     rn[t] = xi * wN[u] / fma(xa, wN[u], 1.0) * (dN[u] - yN[u]);
                     if (!eq) {
                         ds = yS[u] - pS[u];
                         num = fma(ds, ds, num);
                         den = fma(yS[u], yS[u], den);
-                        a.io.s_map[st1 + j] = yS[u];
+                        smap[st1 + j] = yS[u];
                         rs[t] = xi * wS[u] / fma(xa, wS[u], 1.0) * (dS[u] - yS[u]);
                     }
                 }
@@ -544,8 +555,9 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
             // red[] is written once per launch: no barrier needed before it
             const double2 t = block_sum2<NT>(num, den, red);
             if (tid == 0) {
-                a.io.cpart[2 * q] = t.x;
-                a.io.cpart[2 * q + 1] = t.y;
+                double* cp = a.io.cpart + (size_t)map * 2 * a.nq;
+                cp[2 * q] = t.x;
+                cp[2 * q + 1] = t.y;
             }
         }
         if (a.mode == RING_SYN) return;
@@ -597,7 +609,7 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
                 gN.y = 0.0;
                 gS.y = 0.0;
             }
-            double2* g = a.spec + ((size_t)q * a.lp + m) * 2;
+            double2* g = spec + ((size_t)q * a.lp + m) * 2;
             g[0] = gN;
             g[1] = gS;
         }
@@ -761,20 +773,17 @@ dmwf_status build_ring_tables(dmwf_plan* p) {
     return DMWF_OK;
 }
 
-dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const int* ell_syn,
-                        const int* ell_ana, const int* mhi_syn, const int* mhi_ana,
+dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const RingMaps& rm,
                         const RingIO& io, hipStream_t s) {
     RingArgs a;
     a.g = p->geom();
     a.nq = p->nq;
     a.lmax = p->lmax;
     a.lp = p->lp;
-    a.ell_syn = ell_syn;
-    a.ell_ana = ell_ana;
-    a.mhi_syn = mhi_syn;
-    a.mhi_ana = mhi_ana;
     a.spec = spec;
+    a.spec_map = p->ws.spec_map;
     a.io = io;
+    a.rm = rm;
     a.Mq = p->d_ring_M;
     a.blue = p->d_ring_blue;
     a.coff = p->d_ring_coff;
@@ -808,7 +817,7 @@ dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const int* e
             DMWF_HIP(hipStreamWaitEvent(sc, p->ring_fork, 0));
         }
         a.qlist = p->d_ring_class + p->class_off[c];
-        launch_class(c, dim3(nb), class_lds(c), sc, a);
+        launch_class(c, dim3(nb, rm.nm), class_lds(c), sc, a);
         DMWF_HIP(hipGetLastError());
         if (c < kRingClasses - 1) {
             DMWF_HIP(hipEventRecord(p->ring_join[c], sc));

@@ -195,18 +195,22 @@ class Plan:
                        int(max_iter), int(bool(start_final)),
                        ctypes.cast(rep, ctypes.POINTER(ctypes.c_int)) if rep is not None else None,
                        len(replay) if replay is not None else 0, int(bool(want_residual)))
-        ipl = (ctypes.c_int * cap_levels)()
-        xpl = (ctypes.c_double * cap_levels)()
-        lpl = (ctypes.c_int * cap_levels)()
-        st = _Stats(0, 0, 0.0, 0.0, -1.0, cap_levels, ipl, xpl, lpl)
+        # one stats record per map
+        nm = self.nmaps
+        bufs = [((ctypes.c_int * cap_levels)(), (ctypes.c_double * cap_levels)(),
+                 (ctypes.c_int * cap_levels)()) for _ in range(nm)]
+        sts = (_Stats * nm)(*[_Stats(0, 0, 0.0, 0.0, -1.0, cap_levels, *b) for b in bufs])
         status = load().dmwf_solve(self._h, _ptr(cl), _ptr(d), _ptr(ninv), ctypes.byref(sc),
-                                   _ptr(alm), _ptr(out_map), ctypes.byref(st),
+                                   _ptr(alm), _ptr(out_map), sts,
                                    self.ws.data_ptr(), self.ws_bytes, _stream())
         _check(status, "dmwf_solve", allow=() if raise_on_cap else (ERR_NOT_CONVERGED,))
-        nl = min(st.n_levels, cap_levels)
-        stats = SolveStats(st.n_levels, st.n_iter, st.alpha, st.final_cauchy, st.wf_residual,
-                           list(ipl[:nl]), list(xpl[:nl]), list(lpl[:nl]), status)
-        return alm, out_map, stats
+        out = []
+        for st, (ipl, xpl, lpl) in zip(sts, bufs):
+            nl = min(st.n_levels, cap_levels)
+            out.append(SolveStats(st.n_levels, st.n_iter, st.alpha, st.final_cauchy,
+                                  st.wf_residual, list(ipl[:nl]), list(xpl[:nl]),
+                                  list(lpl[:nl]), status))
+        return alm, out_map, (out[0] if nm == 1 else out)
 
     def wf_residual(self, cl, d, ninv, alm) -> float:
         out = ctypes.c_double()
