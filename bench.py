@@ -153,6 +153,95 @@ def copy_calibration(dev):
     print(json.dumps({"copy_calibration_bytes": 1 << 30, "launches": 5}))
 
 
+def batch_group(nside, dev, pairs):
+    """One Nside group of the batched workload: every member map solved
+    together by one plan (one launch per stage for all maps), to eps_final
+    1e-6; then the full-band iteration rate of the batch and of a single map
+    of the group, both measured from the converged states by replaying a fixed
+    number of iterations at xi = alpha (two lengths, set-up cancelled)."""
+    import numpy as np
+    import torch
+
+    import dmwf_inputs as inp
+    from paper_1702_08852_amd import Plan
+
+    idx = inp.batch_members(nside)
+    nm = len(idx)
+    probs = [inp.make_problem("cfg4", nside=nside, index=k) for k in idx]
+    lmax = probs[0].lmax
+    plan = Plan(nside, lmax, nmaps=nm, device=dev)
+    sig = plan.alm2map(torch.tensor(np.stack([q.alm_true for q in probs]), device=dev))
+    noise = torch.tensor(np.stack([q.sigma * q.white for q in probs]), device=dev)
+    mask = torch.tensor(np.stack([q.mask for q in probs]), device=dev)
+    d = (sig + noise).masked_fill(mask, 0.0).contiguous()
+    w = torch.tensor(np.stack([q.ninv for q in probs]), device=dev)
+    cl = torch.tensor(np.stack([q.cl for q in probs]), device=dev)
+    tile, tile_ms = plan.autotune()
+    torch.cuda.synchronize()
+
+    def timed(pl, *a, **k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = pl.solve(*a, **k)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, r
+
+    solve_ms, (alm, smap, sts) = timed(plan, cl, d, w, eps_final=1e-6, eps_coarse=1e-4)
+    iters = [s_.n_iter for s_ in sts]
+    print(f"batch Nside {nside}: {nm} maps solved in {solve_ms / 1e3:.2f} s, tile {tile}",
+          file=sys.stderr, flush=True)
+
+    def pair_rate(pl, cl_, d_, w_, a_):
+        def run(n):
+            pl.profile(True)
+            t = timed(pl, cl_, d_, w_, eps_final=1e-6, start_final=True, alm=a_.clone(),
+                      replay=[n])[0]
+            pr = pl.profile_read()
+            pl.profile(False)
+            return t, pr
+        n0, n1 = 5, 5 + pairs
+        run(n0)
+        (t0, p0), (t1, p1) = run(n0), run(n1)
+        kern = {k: (p1[k][1] - p0[k][1]) / pairs for k in p1 if p1[k][0]}
+        return (t1 - t0) / pairs, kern
+
+    batch_it_ms, batch_kern = pair_rate(plan, cl, d, w, alm)
+    one = Plan(nside, lmax, nmaps=1, device=dev)
+    single_pair_ms, single_kern = pair_rate(one, cl[0].contiguous(), d[0].contiguous(),
+                                            w[0].contiguous(), alm[0].contiguous())
+    f_full = legendre_flops(nside, lmax)
+    return {
+        "nside": nside, "lmax": lmax, "maps": nm,
+        "synthesis_tile": {"rings_per_lane": tile[0], "maps_per_wave": tile[1],
+                           "candidates_ms": {f"{k[0]}x{k[1]}": v for k, v in tile_ms.items()}},
+        "solve_ms": solve_ms, "maps_per_s": nm * 1e3 / solve_ms,
+        "iterations_mean": float(np.mean(iters)), "iterations_max": int(max(iters)),
+        "converged": all(s_.status == 0 for s_ in sts),
+        "batch_iteration_ms": batch_it_ms,
+        "batch_kernel_ms_per_iteration": batch_kern,
+        "single_map_kernel_ms_per_pair": single_kern,
+        "pair_ms_per_map": batch_it_ms / nm,
+        "single_map_pair_ms": single_pair_ms,
+        "batch_gain_per_map": single_pair_ms / (batch_it_ms / nm),
+        "frac_of_fp64_peak": 2 * f_full * nm / (batch_it_ms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS,
+    }
+
+
+def bench_batch(dev, pairs):
+    """The batched workload: 96 maps of Nside {128: 48, 256: 32, 512: 16}, lmax
+    2 Nside, each with its own mask and noise, every group solved as one batch."""
+    import dmwf_inputs as inp
+
+    groups = [batch_group(ns, dev, pairs) for ns, _ in inp.BATCH_GROUPS]
+    tot_ms = sum(g["solve_ms"] for g in groups)
+    nm = sum(g["maps"] for g in groups)
+    return {"workload": ("batched: 96 maps, Nside {128: 48, 256: 32, 512: 16}, lmax 2 Nside, "
+                         "damped C_l, own |b| cut U[5,20] deg + U{50..500} holes of 1 deg and "
+                         "sigma0 U[10,60] uK x lognormal(0, 0.25) per map, eps_final 1e-6, FP64"),
+            "maps": nm, "seconds": tot_ms / 1e3, "maps_per_s": nm * 1e3 / tot_ms,
+            "groups": groups}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +253,9 @@ def main():
     ap.add_argument("--cpu-fraction", type=float, default=1.0,
                     help="fraction of rings (synthesis) and of m (adjoint) the oracle evaluates")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 96-map workload")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only run the batched workload and print its record")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -177,6 +269,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.copy_calibration:
         copy_calibration(dev)
+        return
+    if args.batch_only:
+        print(json.dumps({"batched": bench_batch(dev, 20)}))
         return
     nside = args.nside
     p, plan, cl, d, w, np = make_inputs(nside, dev)
@@ -309,6 +404,10 @@ def main():
                   "iters_per_level": st.iters_per_level, "lmax_per_level": st.lmax_per_level,
                   "kernel_ms_per_solve": {k: v[1] / args.steps for k, v in prof.items() if v[0]}},
     }
+    if not args.no_batch:
+        del plan
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batch(dev, 20)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(nside, lmax, iters, args.cpu_fraction)
     print(json.dumps(out))

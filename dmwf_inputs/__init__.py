@@ -134,6 +134,9 @@ def draw_alm(cl: np.ndarray, rng: np.random.Generator) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # Masks and noise
 # ---------------------------------------------------------------------------
+_TREES: dict = {}
+
+
 def hole_mask(nside: int, n_holes: int, radius_deg: float, rng: np.random.Generator,
               vec: np.ndarray | None = None) -> np.ndarray:
     """Boolean map, True inside any of n_holes discs with centres uniform on the sphere."""
@@ -142,13 +145,17 @@ def hole_mask(nside: int, n_holes: int, radius_deg: float, rng: np.random.Genera
     npix = 12 * nside * nside
     if n_holes == 0:
         return np.zeros(npix, dtype=bool)
-    if vec is None:
-        vec = _unit_vectors(*pixel_centres(nside))
     cz = rng.uniform(-1.0, 1.0, n_holes)
     cphi = rng.uniform(0.0, 2.0 * math.pi, n_holes)
     centres = _unit_vectors(np.arccos(cz), cphi)
     chord = 2.0 * math.sin(math.radians(radius_deg) / 2.0)
-    tree = cKDTree(vec)
+    if vec is None:
+        # the pixel-centre tree of an Nside is built once and reused
+        tree = _TREES.get(nside)
+        if tree is None:
+            tree = _TREES[nside] = cKDTree(_unit_vectors(*pixel_centres(nside)))
+    else:
+        tree = cKDTree(vec)
     mask = np.zeros(npix, dtype=bool)
     for idx in tree.query_ball_point(centres, chord):
         mask[idx] = True

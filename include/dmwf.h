@@ -164,6 +164,18 @@ dmwf_status dmwf_solve(dmwf_plan* plan, const double* dev_cl, const double* dev_
                        double* dev_alm_out, double* dev_map_out, dmwf_stats* stats,
                        void* dev_ws, size_t ws_bytes, void* stream);
 
+/* Pick the tile of the Legendre synthesis for this plan by timing each
+ * candidate on the device: ring pairs per lane {1, 2} x maps per wave
+ * {1, 2, 4, 8} (maps per wave at most nmaps; a wave of several maps computes
+ * the recurrence once for all of them).  Every tile computes each map's sums
+ * in the same order, so the choice changes no result, only the speed of the
+ * calls that follow.  Overwrites the workspace and synchronises the stream.
+ * choice (may be NULL) receives {ring pairs per lane, maps per wave};
+ * ms_out (may be NULL) receives 8 per-launch times in milliseconds, index
+ * 4 (rings - 1) + log2(maps), -1 for candidates not tried. */
+dmwf_status dmwf_autotune(dmwf_plan* plan, void* dev_ws, size_t ws_bytes, void* stream,
+                          int* choice, float* ms_out);
+
 /* ||A x - y|| / ||y|| with A = 1 + C^1/2 Y^H W Y C^1/2, x = C^-1/2 a,
  * y = C^1/2 Y^H W d over modes with C_l > 0 (paper Section 4, Appendix C),
  * norms on a_lm counting m > 0 twice.  Map 0; synchronises the stream. */

@@ -457,7 +457,9 @@ struct Ws {
         return reinterpret_cast<int*>(base + off.lev_iters) + (size_t)k * kMaxLevels;
     }
     int* mhi_tab() const { return reinterpret_cast<int*>(base + off.mhi_tab); }
-    CtrlMaps cmaps() const { return {ctrl(0), levels(0), lev_iters(0), ell(0), ell_ana(0)}; }
+    CtrlMaps cmaps(int k0 = 0) const {
+        return {ctrl(k0), levels(k0), lev_iters(k0), ell(k0), ell_ana(k0)};
+    }
 };
 
 dmwf_status check_ws(const dmwf_plan* p, void* ws, size_t bytes, Ws* out) {
@@ -567,7 +569,6 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
     p->npix = 12LL * N * N;
     p->nalm = (long long)(p->lmax + 1) * (p->lmax + 2) / 2;
     p->omega = 4.0 * kPi / (double)p->npix;
-    p->nchunk_syn = (p->nq + 64 * kSynK - 1) / (64 * kSynK);
     p->nchunk_ana = (p->nq + 64 * kAnaK - 1) / (64 * kAnaK);
     p->lp = (p->lmax + 1 + 3) & ~3;
     if (hipGetDevice(&p->device) != hipSuccess) {
@@ -822,54 +823,123 @@ dmwf_status dmwf_adjoint(dmwf_plan* p, const double* map, double* alm, int scale
     return DMWF_OK;
 }
 
+// Time every synthesis tile on the plan's own shape (all maps, full band,
+// zero input: the instruction stream does not depend on the values) and keep
+// the fastest.  Every tile computes each map's sums in the same order, so the
+// choice changes no result.
+dmwf_status dmwf_autotune(dmwf_plan* p, void* ws, size_t ws_bytes, void* stream, int* choice,
+                          float* ms_out) {
+    if (!p) {
+        set_error("NULL argument");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    Ws W;
+    dmwf_status st = check_ws(p, ws, ws_bytes, &W);
+    if (st != DMWF_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nm = p->nmaps;
+    const bool prof = p->prof;
+    p->prof = false;
+    hipLaunchKernelGGL(k_zero2, dim3(256), dim3(256), 0, s, W.ap(0), (long long)nm * p->ws.alm_map);
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell_full(), p->lmax);
+    DMWF_HIP(hipGetLastError());
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    DMWF_HIP(hipEventCreate(&e0));
+    DMWF_HIP(hipEventCreate(&e1));
+    const LegMaps lm{nm, W.ell_full(), 0, nullptr};
+    float best = 1e30f;
+    int bk = p->syn_k, bmb = p->syn_mb, idx = 0;
+    dmwf_status res = DMWF_OK;
+    for (int k = 1; k <= 2 && res == DMWF_OK; ++k) {
+        for (int mb = 1; mb <= 8 && res == DMWF_OK; mb *= 2, ++idx) {
+            if (mb > nm && mb > 1) {
+                if (ms_out) ms_out[idx] = -1.0f;
+                continue;
+            }
+            p->syn_k = k;
+            const int reps = 3;
+            res = launch_leg_syn(p, W.ap(0), W.spec(0), lm, mb, s);  // warm-up
+            if (res != DMWF_OK) break;
+            if (hipEventRecord(e0, s) != hipSuccess) res = DMWF_ERR_HIP;
+            for (int r = 0; r < reps && res == DMWF_OK; ++r)
+                res = launch_leg_syn(p, W.ap(0), W.spec(0), lm, mb, s);
+            float ms = 0.0f;
+            if (res == DMWF_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                                   hipEventSynchronize(e1) != hipSuccess ||
+                                   hipEventElapsedTime(&ms, e0, e1) != hipSuccess)) {
+                set_error("event timing failed during autotuning");
+                res = DMWF_ERR_HIP;
+            }
+            ms /= reps;
+            if (ms_out) ms_out[idx] = ms;
+            if (res == DMWF_OK && ms < best) {
+                best = ms;
+                bk = k;
+                bmb = mb;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->prof = prof;
+    p->syn_k = bk;
+    p->syn_mb = bmb;
+    if (choice) {
+        choice[0] = bk;
+        choice[1] = bmb;
+    }
+    return res;
+}
+
 }  // extern "C"
 
 namespace dmwf {
 namespace {
 
 // The iteration body shared by dmwf_dm_iterate (map 0, host parameters) and
-// the solve loop (every map, parameters from the per-map control blocks):
-// harmonic step from the residual spectrum in the workspace, synthesis,
-// pixel step.  The solve loop ends the iteration with each map's level
-// decision; dmwf_dm_iterate sums the Cauchy partials into cauchy_out.
-dmwf_status iterate_body(dmwf_plan* p, const Ws& W, int nm, double xi, double alpha, double mu,
-                         const double* cl, const double* d, const double* w, double2* a,
-                         double* s_map, int first_pix, const int* mhi_ana, double* cauchy_out,
-                         DevCtrl* ctrl, hipStream_t s) {
-    const LegMaps lm{nm, W.ell(0), 1, ctrl};
-    dmwf_status st = launch_leg_ana(p, W.spec(0), W.part(0), lm, p->ana_mb, s);
+// the solve loop (a group of nm maps from map k0, parameters from the per-map
+// control blocks): harmonic step from the residual spectrum in the
+// workspace, synthesis, pixel step.  cl, d, w, a and s_map point at map k0's
+// slices.  The solve loop ends the iteration with each map's level decision;
+// dmwf_dm_iterate sums the Cauchy partials into cauchy_out.
+dmwf_status iterate_body(dmwf_plan* p, const Ws& W, int k0, int nm, double xi, double alpha,
+                         double mu, const double* cl, const double* d, const double* w,
+                         double2* a, double* s_map, int first_pix, const int* mhi_ana,
+                         double* cauchy_out, DevCtrl* ctrl, hipStream_t s) {
+    const LegMaps lm{nm, W.ell(k0), 1, ctrl};
+    dmwf_status st = launch_leg_ana(p, W.spec(k0), W.part(k0), lm, p->ana_mb, s);
     if (st != DMWF_OK) return st;
     {
         ProfScope ps(p, s, PROF_DIAG);
-        DiagArgs da{a,       p->nalm, W.ap(0), p->ws.alm_map, W.part(0), p->ws.part_map,
+        DiagArgs da{a,       p->nalm, W.ap(k0), p->ws.alm_map, W.part(k0), p->ws.part_map,
                     (size_t)p->nalm + kTablePad, p->nchunk_ana, p->d_g, cl, mu, xi * p->omega,
-                    p->omega, W.ell(0), 1, p->lmax, ctrl};
+                    p->omega, W.ell(k0), 1, p->lmax, ctrl};
         hipLaunchKernelGGL(k_diag, alm_grid(p->lmax, 256, nm), dim3(256), 0, s, da);
     }
     DMWF_HIP(hipGetLastError());
-    st = launch_leg_syn(p, W.ap(0), W.spec(0), lm, p->syn_mb, s);
+    st = launch_leg_syn(p, W.ap(k0), W.spec(k0), lm, p->syn_mb, s);
     if (st != DMWF_OK) return st;
     RingIO io{};
     io.d = d;
     io.w = w;
     io.s_map = s_map;
-    io.cpart = W.cpart(0, p->nq);
+    io.cpart = W.cpart(k0, p->nq);
     io.xi = xi;
     io.alpha = alpha;
     io.first = first_pix;
     io.ctrl = ctrl;
-    io.mhi_tab = W.mhi_tab();
+    io.mhi_tab = W.mhi_tab() + (size_t)k0 * kMaxLevels * p->nq;
     io.pix_map = p->npix;
-    const RingMaps rm{nm, W.ell(0), W.ell_ana(0), 1, W.mhi(0, p->nq), mhi_ana, 0};
-    st = launch_ring(p, RING_ITER, W.spec(0), rm, io, s);
+    const RingMaps rm{nm, W.ell(k0), W.ell_ana(k0), 1, W.mhi(k0, p->nq), mhi_ana, 0};
+    st = launch_ring(p, RING_ITER, W.spec(k0), rm, io, s);
     if (st != DMWF_OK) return st;
     {
         ProfScope ps(p, s, PROF_REDUCE);
         if (ctrl)
-            hipLaunchKernelGGL(k_control, dim3(nm), dim3(256), 0, s, W.cpart(0, p->nq), p->nq,
-                               W.cmaps(), W.mdbl(0));
+            hipLaunchKernelGGL(k_control, dim3(nm), dim3(256), 0, s, W.cpart(k0, p->nq), p->nq,
+                               W.cmaps(k0), W.mdbl(k0));
         else
-            hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, s, W.cpart(0, p->nq), p->nq,
+            hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, s, W.cpart(k0, p->nq), p->nq,
                                cauchy_out);
     }
     DMWF_HIP(hipGetLastError());
@@ -960,8 +1030,9 @@ dmwf_status dmwf_dm_iterate(dmwf_plan* p, double xi, double alpha, const double*
         st = launch_ring(p, RING_ANA_FIRST, W.spec(0), rm, io, s);
         if (st != DMWF_OK) return st;
     }
-    return iterate_body(p, W, 1, xi, alpha, mu, cl, d, ninv, reinterpret_cast<double2*>(alm_state),
-                        s_map, first ? 1 : 0, p->d_mhi_full, cauchy2, nullptr, s);
+    return iterate_body(p, W, 0, 1, xi, alpha, mu, cl, d, ninv,
+                        reinterpret_cast<double2*>(alm_state), s_map, first ? 1 : 0,
+                        p->d_mhi_full, cauchy2, nullptr, s);
 }
 
 dmwf_status dmwf_wf_residual(dmwf_plan* p, const double* cl, const double* d, const double* ninv,
@@ -1154,7 +1225,7 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
     // host; iterations enqueued after a map's stop do nothing for that map.
     auto enqueue = [&](int nit, int slot) -> dmwf_status {
         for (int i = 0; i < nit; ++i) {
-            dmwf_status e = iterate_body(p, W, nm, 0.0, 0.0, 0.0, cl_all, d_all, ninv_all, a,
+            dmwf_status e = iterate_body(p, W, 0, nm, 0.0, 0.0, 0.0, cl_all, d_all, ninv_all, a,
                                          map_all, first_pix, nullptr, nullptr, W.ctrl(0), s);
             if (e != DMWF_OK) return e;
             first_pix = 0;

@@ -129,9 +129,10 @@ struct dmwf_plan {
     int nside, lmax, nmaps, nq, nrings, device;
     long long npix, nalm;
     int nchunk_ana, nchunk_syn;
-    // maps per wave of the Legendre kernels (1, 2 or 4): the recurrence is
-    // computed once for all of them; set by dmwf_autotune or by default
-    int syn_mb = 1, ana_mb = 1;
+    // Legendre synthesis tile: ring pairs per lane (1 or 2) and maps per wave
+    // (1, 2, 4 or 8; the recurrence is computed once for all of them); set by
+    // dmwf_autotune or by default.  The analysis takes one map per wave.
+    int syn_k = 2, syn_mb = 1, ana_mb = 1;
     int lp;        // m-row length of the ring-major F/G buffer, lmax+1 rounded up to 4
     double omega;  // 4 pi / Npix
     // device tables

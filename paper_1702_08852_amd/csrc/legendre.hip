@@ -670,14 +670,28 @@ dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const
               lm.ell,       lm.ell_stride, lm.ctrl,     p->lmax,  p->nq,
               p->lp,        lm.nm};
     ProfScope ps(p, s, PROF_LEG_SYN);
-    const int mb = pick_mb(mb_want, lm.nm, 4);
-    const dim3 grid(p->nchunk_syn * leg_groups8(p), (lm.nm + mb - 1) / mb);
+    const int mb = pick_mb(mb_want, lm.nm, 8);
+    const int k = p->syn_k == 1 ? 1 : 2;
+    const int nchunk = (p->nq + 64 * k - 1) / (64 * k);
+    const dim3 grid(nchunk * leg_groups8(p), (lm.nm + mb - 1) / mb);
     const dim3 block(64 * kLegWaves);
-    switch (mb) {
-        case 4: hipLaunchKernelGGL((k_leg_syn<kSynK, 4>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_leg_syn<kSynK, 2>), grid, block, 0, s, a); break;
-        default: hipLaunchKernelGGL((k_leg_syn<kSynK, 1>), grid, block, 0, s, a); break;
+#define DMWF_SYN(K, MB) hipLaunchKernelGGL((k_leg_syn<K, MB>), grid, block, 0, s, a)
+    if (k == 1) {
+        switch (mb) {
+            case 8: DMWF_SYN(1, 8); break;
+            case 4: DMWF_SYN(1, 4); break;
+            case 2: DMWF_SYN(1, 2); break;
+            default: DMWF_SYN(1, 1); break;
+        }
+    } else {
+        switch (mb) {
+            case 8: DMWF_SYN(2, 8); break;
+            case 4: DMWF_SYN(2, 4); break;
+            case 2: DMWF_SYN(2, 2); break;
+            default: DMWF_SYN(2, 1); break;
+        }
     }
+#undef DMWF_SYN
     DMWF_HIP(hipGetLastError());
     return DMWF_OK;
 }

@@ -358,7 +358,6 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     const double xi_ = ctrl ? (a.pix == PIX_CRES ? ctrl->alpha : ctrl->xi) : a.io.xi;
     const double alpha_ = ctrl ? ctrl->alpha : a.io.alpha;
     const int tid = threadIdx.x;
-    double rn[J], rs[J];
     // m per thread and batch in the fold and unfold
     constexpr int FB = NT >= 512 ? 5 : 6;
 
@@ -449,6 +448,7 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
         }
     } else {
         // analysis only: the input comes from the pixels
+        double rn[J], rs[J];
 #pragma unroll
         for (int t = 0; t < J; ++t) {
             const int j = tid + t * NT;
@@ -491,11 +491,13 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
             }
         }
         // y_j = IDFT(Z)_j: blue: c_j buf_j; else conj(buf_j).  s^N = Re y, s^S = Im y.
-        // Pixel data are loaded for all of the thread's pixels first, then
+        // Pixel data are loaded for JH of the thread's pixels first, then
         // combined and stored, so the loads of one pixel never wait on the
-        // store of another.
+        // store of another.  The residual r goes straight back into the slot
+        // of y as the analysis input z_j = r^N_j + i r^S_j [times conj(c_j)]:
+        // each slot is read and written by the same thread only.
         double num = 0.0, den = 0.0;
-        constexpr int JH = J;  // all of the thread's pixels in one batch of loads
+        constexpr int JH = J < 4 ? J : 4;
 #pragma unroll
         for (int t0 = 0; t0 < J; t0 += JH) {
             double yN[JH], yS[JH], dN[JH], dS[JH], wN[JH], wS[JH], pN[JH], pS[JH];
@@ -523,34 +525,40 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
             }
 #pragma unroll
             for (int u = 0; u < JH; ++u) {
-                const int t = t0 + u;
-                const int j = tid + t * NT;
-                rn[t] = 0.0;
-                rs[t] = 0.0;
+                const int j = tid + (t0 + u) * NT;
                 if (j >= n) continue;
+                double rn = 0.0, rs = 0.0;
                 if (a.mode == RING_SYN) {
                     mout[st0 + j] = yN[u];
                     if (!eq) mout[st1 + j] = yS[u];
+                    continue;
                 } else if (a.mode == RING_SYN_WRES) {
-                    rn[t] = wN[u] * (dN[u] - yN[u]);
-                    rs[t] = eq ? 0.0 : wS[u] * (dS[u] - yS[u]);
+                    rn = wN[u] * (dN[u] - yN[u]);
+                    rs = eq ? 0.0 : wS[u] * (dS[u] - yS[u]);
                 } else {
                     const double xi = xi_, xa = xi_ - alpha_;
                     double ds = yN[u] - pN[u];
                     num = fma(ds, ds, num);
                     den = fma(yN[u], yN[u], den);
                     smap[st0 + j] = yN[u];
-                    rn[t] = xi * wN[u] / fma(xa, wN[u], 1.0) * (dN[u] - yN[u]);
+                    rn = xi * wN[u] / fma(xa, wN[u], 1.0) * (dN[u] - yN[u]);
                     if (!eq) {
                         ds = yS[u] - pS[u];
                         num = fma(ds, ds, num);
                         den = fma(yS[u], yS[u], den);
                         smap[st1 + j] = yS[u];
-                        rs[t] = xi * wS[u] / fma(xa, wS[u], 1.0) * (dS[u] - yS[u]);
+                        rs = xi * wS[u] / fma(xa, wS[u], 1.0) * (dS[u] - yS[u]);
                     }
                 }
+                double2 z = make_double2(rn, rs);
+                if (blue) z = cmul(z, conj2(ch[j]));
+                buf[pad(j)] = z;
             }
         }
+        // zero padding of the analysis input (Bluestein rings): slots no
+        // thread reads in this stage
+        if (a.mode != RING_SYN)
+            for (int j = n + tid; j < M; j += NT) buf[pad(j)] = make_double2(0.0, 0.0);
         if (a.mode == RING_ITER) {
             // red[] is written once per launch: no barrier needed before it
             const double2 t = block_sum2<NT>(num, den, red);
@@ -561,8 +569,6 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
             }
         }
         if (a.mode == RING_SYN) return;
-        lds_barrier();
-        ana_input<NT, J>(buf, rn, rs, n, M, blue, ch, tid);
         lds_barrier();
     }
 #pragma unroll 1
@@ -653,7 +659,7 @@ void launch_class(int cls, dim3 grid, size_t lds, hipStream_t s, const RingArgs&
     switch (cls) {
         case 0: hipLaunchKernelGGL((k_ring_fft<128, 8, 0>), grid, dim3(128), lds, s, a); break;
         case 1: hipLaunchKernelGGL((k_ring_fft<256, 8, 2048>), grid, dim3(256), lds, s, a); break;
-        case 2: hipLaunchKernelGGL((k_ring_fft<512, 8, 4096>), grid, dim3(512), lds, s, a); break;
+        case 2: hipLaunchKernelGGL((k_ring_fft<256, 16, 4096>), grid, dim3(256), lds, s, a); break;
         default: hipLaunchKernelGGL((k_ring_fft<512, 8, 8192>), grid, dim3(512), lds, s, a); break;
     }
 }

@@ -70,6 +70,7 @@ def load() -> ctypes.CDLL:
     lib.dmwf_dm_iterate.argtypes = [vp, cd, cd, vp, vp, vp, vp, vp, vp, ci, vp, sz, vp]
     lib.dmwf_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(_Schedule), vp, vp,
                                ctypes.POINTER(_Stats), vp, sz, vp]
+    lib.dmwf_autotune.argtypes = [vp, vp, sz, vp, ctypes.POINTER(ci), ctypes.POINTER(ctypes.c_float)]
     lib.dmwf_wf_residual.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(cd), vp, sz, vp]
     lib.dmwf_profile_enable.argtypes = [vp, ci]
     lib.dmwf_profile_read.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ctypes.c_char_p),
@@ -211,6 +212,16 @@ class Plan:
                                   st.wf_residual, list(ipl[:nl]), list(xpl[:nl]),
                                   list(lpl[:nl]), status))
         return alm, out_map, (out[0] if nm == 1 else out)
+
+    def autotune(self):
+        """Time the synthesis tiles on this plan's shape and keep the fastest.
+        Returns ((rings per lane, maps per wave), {(rings, maps): ms})."""
+        ch = (ctypes.c_int * 2)()
+        ms = (ctypes.c_float * 8)()
+        _check(load().dmwf_autotune(self._h, self.ws.data_ptr(), self.ws_bytes, _stream(), ch, ms),
+               "dmwf_autotune")
+        times = {(1 + i // 4, 1 << (i % 4)): float(ms[i]) for i in range(8) if ms[i] >= 0.0}
+        return (int(ch[0]), int(ch[1])), times
 
     def wf_residual(self, cl, d, ninv, alm) -> float:
         out = ctypes.c_double()
