@@ -569,7 +569,12 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
     p->npix = 12LL * N * N;
     p->nalm = (long long)(p->lmax + 1) * (p->lmax + 2) / 2;
     p->omega = 4.0 * kPi / (double)p->npix;
-    p->nchunk_ana = (p->nq + 64 * kAnaK - 1) / (64 * kAnaK);
+    // analysis tile: 8 ring pairs per lane, 4 where a wave of 8 would leave
+    // lanes idle (at most 256 ring pairs); the partial-sum buffer holds the
+    // chunks of the smallest tile the autotuner may pick
+    p->ana_k = p->nq <= 256 ? 4 : 8;
+    p->ana_k_min = p->nq <= 512 ? 4 : 8;
+    p->nchunk_ana = (p->nq + 64 * p->ana_k - 1) / (64 * p->ana_k);
     p->lp = (p->lmax + 1 + 3) & ~3;
     if (hipGetDevice(&p->device) != hipSuccess) {
         set_error("hipGetDevice failed");
@@ -671,7 +676,7 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
     WsLayout& w = p->ws;
     const size_t nm = (size_t)p->nmaps;
     w.spec_map = (long long)p->lp * nq * 2;
-    w.part_map = (long long)p->nchunk_ana * ntab;
+    w.part_map = (long long)((nq + 64 * p->ana_k_min - 1) / (64 * p->ana_k_min)) * ntab;
     w.alm_map = (long long)ntab;
     size_t off = 0;
     w.spec = off;
@@ -823,6 +828,21 @@ dmwf_status dmwf_adjoint(dmwf_plan* p, const double* map, double* alm, int scale
     return DMWF_OK;
 }
 
+dmwf_status dmwf_set_tiles(dmwf_plan* p, int syn_k, int syn_mb, int ana_k) {
+    if (!p || (syn_k != 1 && syn_k != 2) ||
+        (syn_mb != 1 && syn_mb != 2 && syn_mb != 4 && syn_mb != 8) ||
+        (ana_k != 4 && ana_k != 8) || ana_k < p->ana_k_min) {
+        set_error("tiles: synthesis ring pairs per lane 1 or 2, maps per wave 1, 2, 4 or 8, "
+                  "analysis ring pairs per lane 4 (nside <= 256) or 8");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    p->syn_k = syn_k;
+    p->syn_mb = syn_mb;
+    p->ana_k = ana_k;
+    p->nchunk_ana = (p->nq + 64 * ana_k - 1) / (64 * ana_k);
+    return DMWF_OK;
+}
+
 // Time every synthesis tile on the plan's own shape (all maps, full band,
 // zero input: the instruction stream does not depend on the values) and keep
 // the fastest.  Every tile computes each map's sums in the same order, so the
@@ -879,14 +899,44 @@ dmwf_status dmwf_autotune(dmwf_plan* p, void* ws, size_t ws_bytes, void* stream,
             }
         }
     }
+    p->syn_k = bk;
+    p->syn_mb = bmb;
+    // analysis: ring pairs per lane 8, and 4 where the buffers allow it
+    float abest = 1e30f;
+    int ak = p->ana_k;
+    for (int k = p->ana_k_min; k <= 8 && res == DMWF_OK; k *= 2) {
+        p->ana_k = k;
+        p->nchunk_ana = (p->nq + 64 * k - 1) / (64 * k);
+        const int reps = 3;
+        res = launch_leg_ana(p, W.spec(0), W.part(0), lm, 1, s);
+        if (res != DMWF_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) res = DMWF_ERR_HIP;
+        for (int r = 0; r < reps && res == DMWF_OK; ++r)
+            res = launch_leg_ana(p, W.spec(0), W.part(0), lm, 1, s);
+        float ms = 0.0f;
+        if (res == DMWF_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                               hipEventSynchronize(e1) != hipSuccess ||
+                               hipEventElapsedTime(&ms, e0, e1) != hipSuccess)) {
+            set_error("event timing failed during autotuning");
+            res = DMWF_ERR_HIP;
+        }
+        ms /= reps;
+        if (ms_out) ms_out[8 + (k == 4 ? 0 : 1)] = ms;
+        if (res == DMWF_OK && ms < abest) {
+            abest = ms;
+            ak = k;
+        }
+    }
+    if (ms_out && p->ana_k_min > 4) ms_out[8] = -1.0f;
+    p->ana_k = ak;
+    p->nchunk_ana = (p->nq + 64 * ak - 1) / (64 * ak);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     p->prof = prof;
-    p->syn_k = bk;
-    p->syn_mb = bmb;
     if (choice) {
         choice[0] = bk;
         choice[1] = bmb;
+        choice[2] = ak;
     }
     return res;
 }

@@ -12,19 +12,10 @@
 
 namespace dmwf {
 
-// Rings per lane in the Legendre kernels: a wave covers 64*K ring pairs.
-#ifndef DMWF_SYN_K
-#define DMWF_SYN_K 2
-#endif
-#ifndef DMWF_ANA_K
-#define DMWF_ANA_K 8
-#endif
 // Waves per Legendre workgroup, each on its own m (consecutive m share a CU).
 #ifndef DMWF_LEG_WAVES
 #define DMWF_LEG_WAVES 2
 #endif
-constexpr int kSynK = DMWF_SYN_K;
-constexpr int kAnaK = DMWF_ANA_K;
 constexpr int kLegWaves = DMWF_LEG_WAVES;
 // l values per block of the Legendre kernels: recurrences start only at the
 // first l of a block (counted from m), and the analysis reduces once per block.
@@ -129,10 +120,12 @@ struct dmwf_plan {
     int nside, lmax, nmaps, nq, nrings, device;
     long long npix, nalm;
     int nchunk_ana, nchunk_syn;
-    // Legendre synthesis tile: ring pairs per lane (1 or 2) and maps per wave
-    // (1, 2, 4 or 8; the recurrence is computed once for all of them); set by
-    // dmwf_autotune or by default.  The analysis takes one map per wave.
-    int syn_k = 2, syn_mb = 1, ana_mb = 1;
+    // Legendre tiles, set by default and by dmwf_autotune.  Synthesis: ring
+    // pairs per lane (1 or 2) and maps per wave (1, 2, 4 or 8; the recurrence
+    // is computed once for all of them).  Analysis: ring pairs per lane (4 or
+    // 8; nchunk_ana follows), one map per wave.
+    int syn_k = 2, syn_mb = 1, ana_mb = 1, ana_k = 8;
+    int ana_k_min = 8;  // smallest analysis tile the partial-sum buffer holds
     int lp;        // m-row length of the ring-major F/G buffer, lmax+1 rounded up to 4
     double omega;  // 4 pi / Npix
     // device tables

@@ -705,7 +705,10 @@ dmwf_status launch_leg_ana(dmwf_plan* p, const double2* spec, double2* part, con
               p->nq,    p->lp,          lm.nm};
     ProfScope ps(p, s, PROF_LEG_ANA);
     const dim3 grid(p->nchunk_ana * leg_groups8(p), lm.nm);
-    hipLaunchKernelGGL((k_leg_ana<kAnaK, 1>), grid, dim3(64 * kLegWaves), 0, s, a);
+    if (p->ana_k == 4)
+        hipLaunchKernelGGL((k_leg_ana<4, 1>), grid, dim3(64 * kLegWaves), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_leg_ana<8, 1>), grid, dim3(64 * kLegWaves), 0, s, a);
     DMWF_HIP(hipGetLastError());
     return DMWF_OK;
 }
