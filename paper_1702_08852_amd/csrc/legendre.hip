@@ -196,6 +196,8 @@ struct SynArgs {
 // L2 hits, and it measured faster than LDS staging there.
 constexpr int kChunk = 64;
 
+
+
 // Orders this wave's LDS writes before its later LDS reads (and reads before
 // later writes); the other waves of the workgroup use their own LDS region.
 __device__ __forceinline__ void wave_lds_sync() {
@@ -332,13 +334,20 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn(SynArgs a) {
 #pragma unroll
         for (int i = 0; i < MB; ++i)
             ap[i] = a.ap + (long long)min(mg + i, a.nm - 1) * a.ap_map + base;
-        // every start is the first l of a 16-l block counted from m
+        // every start is the first l of a 16-l block counted from m.  The
+        // coefficients of PAIRS even/odd pairs are fetched together: all of a
+        // block's for one map, fewer for several maps, so that they fit the
+        // scalar registers (measured best: 4 pairs for 2 and 4 maps, 2 for 8)
+        constexpr int PAIRS = MB >= 8 ? 2 : (MB >= 2 ? 4 : kLegB / 2);
         int l = lo;
         for (; l + kLegB - 1 <= ell; l += kLegB) {
             if (l <= hi) inject<K>(l, ls, s0, s1, p1, p2);
+#pragma unroll 1
+            for (int j0 = 0; j0 < kLegB / 2; j0 += PAIRS) {
 #pragma unroll
-            for (int j = 0; j < kLegB / 2; ++j)
-                syn_pair<K, MB>(l + 2 * j, true, A, ap, x, p1, p2, er, ei, orr, oi);
+                for (int j = 0; j < PAIRS; ++j)
+                    syn_pair<K, MB>(l + 2 * (j0 + j), true, A, ap, x, p1, p2, er, ei, orr, oi);
+            }
         }
         if (l <= ell) {
             if (l <= hi) inject<K>(l, ls, s0, s1, p1, p2);
