@@ -658,7 +658,7 @@ int ring_class(int M) { return M <= 1024 ? 0 : (M == 2048 ? 1 : (M == 4096 ? 2 :
 void launch_class(int cls, dim3 grid, size_t lds, hipStream_t s, const RingArgs& a) {
     switch (cls) {
         case 0: hipLaunchKernelGGL((k_ring_fft<64, 16, 0>), grid, dim3(64), lds, s, a); break;
-        case 1: hipLaunchKernelGGL((k_ring_fft<256, 8, 2048>), grid, dim3(256), lds, s, a); break;
+        case 1: hipLaunchKernelGGL((k_ring_fft<128, 16, 2048>), grid, dim3(128), lds, s, a); break;
         case 2: hipLaunchKernelGGL((k_ring_fft<256, 16, 4096>), grid, dim3(256), lds, s, a); break;
         default: hipLaunchKernelGGL((k_ring_fft<512, 8, 8192>), grid, dim3(512), lds, s, a); break;
     }
