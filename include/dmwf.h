@@ -65,7 +65,7 @@ typedef struct dmwf_plan dmwf_plan;
 typedef struct {
     int nside;     /* power of two, 1 .. 8192                                  */
     int lmax;      /* 0 .. 3 nside - 1                                         */
-    int nmaps;     /* >= 1; the maps of a plan are transformed and solved together */
+    int nmaps;     /* 1 .. 65535; the maps of a plan are transformed and solved together */
     int precision; /* DMWF_FP64                                                */
 } dmwf_plan_desc;
 

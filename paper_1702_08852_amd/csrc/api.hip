@@ -548,8 +548,8 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
         set_error("lmax must be in [0, 3 nside - 1]");
         return DMWF_ERR_INVALID_ARG;
     }
-    if (desc->nmaps < 1) {
-        set_error("nmaps must be >= 1");
+    if (desc->nmaps < 1 || desc->nmaps > 65535) {
+        set_error("nmaps must be in [1, 65535] (the maps of a launch are a grid dimension)");
         return DMWF_ERR_INVALID_ARG;
     }
     if (desc->precision != DMWF_FP64) {

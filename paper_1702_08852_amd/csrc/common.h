@@ -119,7 +119,7 @@ struct LegMaps {
 struct dmwf_plan {
     int nside, lmax, nmaps, nq, nrings, device;
     long long npix, nalm;
-    int nchunk_ana, nchunk_syn;
+    int nchunk_ana;  // analysis ring chunks (partial-sum rows per map)
     // Legendre tiles, set by default and by dmwf_autotune.  Synthesis: ring
     // pairs per lane (1 or 2) and maps per wave (1, 2, 4 or 8; the recurrence
     // is computed once for all of them).  Analysis: ring pairs per lane (4 or
