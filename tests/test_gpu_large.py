@@ -3,7 +3,8 @@
 Full transforms up to Nside 512; at the paper-scale Nside 1024 / lmax 2048
 (the benchmark's launch configuration) the oracle evaluates sampled rings and
 sampled m one by one, and one full iteration through the C ABI is checked
-against an oracle iteration.
+against an oracle iteration.  The batched workload's Nside 512 group is
+checked the same way in its autotuned launch configuration.
 """
 import math
 
@@ -134,3 +135,52 @@ def test_dm_iterate_nside1024_cfg3_first_iteration():
     assert rel(mine, ref) < 1e-11
     cc = c2.cpu().numpy()
     assert math.isfinite(cc[0]) and cc[0] == pytest.approx(cc[1], rel=1e-12)  # s_prev = 0
+
+
+def test_batched_nside512_group_sampled():
+    """The batched workload's Nside 512 group (16 maps of its own recipe) in the
+    autotuned launch configuration the benchmark times: batched transforms on
+    sampled rings and m of first, middle and last maps, and one full-band
+    iteration of the batched solve against the oracle for two maps."""
+    import torch
+    from paper_1702_08852_amd import Plan
+    dev = device()
+    nside, lmax = 512, 1024
+    idx = inp.batch_members(nside)
+    nm = len(idx)
+    plan = Plan(nside, lmax, nmaps=nm, device=dev)
+    plan.autotune()
+    a = np.stack([inp.random_alm(lmax, 900 + k) for k in range(nm)])
+    got = plan.alm2map(torch.tensor(a, device=dev)).cpu().numpy()
+    z, st, nph, p0, start = oracle.rings(nside)
+    rings = [1, 2, 255, 256, 511, 512, 1000, 1023, 1024, 1025, 2000, 2046, 2047]
+    for k in (0, 7, nm - 1):
+        ref = oracle.alm2map_rings(a[k], nside, lmax, rings)
+        mine = np.concatenate([got[k, start[r - 1]:start[r - 1] + nph[r - 1]] for r in rings])
+        assert rel(mine, ref) < 1e-12, k
+    mp = np.stack([inp.random_map(nside, 950 + k) for k in range(nm)])
+    got = plan.adjoint(torch.tensor(mp, device=dev)).cpu().numpy()
+    ms = [0, 1, 255, 256, 511, 512, 1000, 1023, 1024]
+    for k in (0, nm - 1):
+        ref = oracle.adjoint_m(mp[k], nside, lmax, ms)
+        for m, v in ref.items():
+            k0 = oracle.alm_index(m, m, lmax)
+            assert rel(got[k, k0:k0 + lmax - m + 1], v) < 1e-12, (k, m)
+    # one full-band iteration at xi = alpha from a = 0, every map at once
+    probs = [inp.make_problem("cfg4", nside=nside, index=i) for i in idx]
+    T = oracle.SphereTransforms(nside, lmax)
+    ds = [q.data_map(T.synth(q.alm_true)) for q in probs[:2]]
+    d = np.stack(ds + [probs[k].sigma * probs[k].white * ~probs[k].mask for k in range(2, nm)])
+    w = np.stack([q.ninv for q in probs])
+    cl = np.stack([q.cl for q in probs])
+    a0 = torch.zeros((nm, oracle.n_alm(lmax), 2), dtype=torch.float64, device=dev)
+    alm, smap, sts = plan.solve(torch.tensor(cl, device=dev), torch.tensor(d, device=dev),
+                                torch.tensor(w, device=dev), start_final=True, alm=a0,
+                                replay=[1])
+    alm, smap = alm.cpu().numpy(), smap.cpu().numpy()
+    for k in range(2):
+        ref = dm.solve(T, d[k], w[k], cl[k], start_final=True, alm0=np.zeros_like(alm[k]),
+                       replay=[1])
+        assert sts[k].n_iter == 1 and ref.n_iter == 1
+        assert rel(alm[k], ref.alm) < 1e-11
+        assert rel(smap[k], ref.map) < 1e-11
