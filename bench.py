@@ -213,7 +213,8 @@ def batch_group(nside, dev, pairs):
     return {
         "nside": nside, "lmax": lmax, "maps": nm,
         "legendre_tiles": {"synthesis_rings_per_lane": tile[0], "synthesis_maps_per_wave": tile[1],
-                           "analysis_rings_per_lane": tile[2], "candidates_ms": tile_ms},
+                           "analysis_rings_per_lane": tile[2], "analysis_maps_per_wave": tile[3],
+                           "candidates_ms": tile_ms},
         "solve_ms": solve_ms, "maps_per_s": nm * 1e3 / solve_ms,
         "iterations_mean": float(np.mean(iters)), "iterations_max": int(max(iters)),
         "converged": all(s_.status == 0 for s_ in sts),

@@ -166,16 +166,17 @@ dmwf_status dmwf_solve(dmwf_plan* plan, const double* dev_cl, const double* dev_
 
 /* Pick the tiles of the Legendre stages for this plan by timing each
  * candidate on the device.  Synthesis: ring pairs per lane {1, 2} x maps per
- * wave {1, 2, 4, 8} (maps per wave at most nmaps; a wave of several maps
- * computes the recurrence once for all of them).  Analysis: ring pairs per
- * lane {4, 8} (4 only for nside <= 256).  Every synthesis tile computes each
- * map's sums in the same order, so its choice changes no result; the
- * analysis tile changes the order in which ring pairs are summed (rounding
- * only).  Overwrites the workspace and synchronises the stream.  choice (may
- * be NULL) receives {synthesis ring pairs per lane, maps per wave, analysis
- * ring pairs per lane}; ms_out (may be NULL) receives 10 per-launch times in
- * milliseconds, synthesis at 4 (rings - 1) + log2(maps), analysis at 8 (4 per
- * lane) and 9 (8 per lane), -1 for candidates not tried. */
+ * wave {1, 2, 4, 8}.  Analysis: ring pairs per lane {4, 8} (4 only for
+ * nside <= 256) x maps per wave {1, 2}.  Maps per wave are at most nmaps; a
+ * wave of several maps computes the recurrence once for all of them.  The
+ * maps per wave and the synthesis ring pairs per lane change no result (each
+ * map's sums run in the same order); the analysis ring pairs per lane change
+ * the order in which ring pairs are summed (rounding only).  Overwrites the
+ * workspace and synchronises the stream.  choice (may be NULL) receives
+ * {synthesis ring pairs per lane, synthesis maps per wave, analysis ring
+ * pairs per lane, analysis maps per wave}; ms_out (may be NULL) receives 12
+ * per-launch times in milliseconds: synthesis at 4 (rings - 1) + log2(maps),
+ * analysis at 8 + 2 (rings == 8) + (maps - 1); -1 for candidates not tried. */
 dmwf_status dmwf_autotune(dmwf_plan* plan, void* dev_ws, size_t ws_bytes, void* stream,
                           int* choice, float* ms_out);
 
@@ -183,7 +184,7 @@ dmwf_status dmwf_autotune(dmwf_plan* plan, void* dev_ws, size_t ws_bytes, void* 
  * maps per wave above nmaps act as nmaps.  The workspace's analysis partial
  * sums and residual spectrum are invalid afterwards (the next dmwf_dm_iterate
  * call needs first != 0).  DMWF_ERR_INVALID_ARG for other values. */
-dmwf_status dmwf_set_tiles(dmwf_plan* plan, int syn_k, int syn_mb, int ana_k);
+dmwf_status dmwf_set_tiles(dmwf_plan* plan, int syn_k, int syn_mb, int ana_k, int ana_mb);
 
 /* ||A x - y|| / ||y|| with A = 1 + C^1/2 Y^H W Y C^1/2, x = C^-1/2 a,
  * y = C^1/2 Y^H W d over modes with C_l > 0 (paper Section 4, Appendix C),

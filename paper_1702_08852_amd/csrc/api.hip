@@ -717,9 +717,9 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
     }
     // maps per wave of the Legendre kernels until dmwf_autotune measures
     // better: the synthesis shares its recurrence across up to four maps, the
-    // analysis (whose lane reduction grows with the maps) keeps one
+    // analysis (whose lane reduction and registers grow with the maps) across two
     p->syn_mb = p->nmaps >= 4 ? 4 : (p->nmaps >= 2 ? 2 : 1);
-    p->ana_mb = 1;
+    p->ana_mb = p->nmaps >= 2 ? 2 : 1;
     *out = p;
     return DMWF_OK;
 }
@@ -828,25 +828,24 @@ dmwf_status dmwf_adjoint(dmwf_plan* p, const double* map, double* alm, int scale
     return DMWF_OK;
 }
 
-dmwf_status dmwf_set_tiles(dmwf_plan* p, int syn_k, int syn_mb, int ana_k) {
+dmwf_status dmwf_set_tiles(dmwf_plan* p, int syn_k, int syn_mb, int ana_k, int ana_mb) {
     if (!p || (syn_k != 1 && syn_k != 2) ||
         (syn_mb != 1 && syn_mb != 2 && syn_mb != 4 && syn_mb != 8) ||
-        (ana_k != 4 && ana_k != 8) || ana_k < p->ana_k_min) {
-        set_error("tiles: synthesis ring pairs per lane 1 or 2, maps per wave 1, 2, 4 or 8, "
-                  "analysis ring pairs per lane 4 (nside <= 256) or 8");
+        (ana_k != 4 && ana_k != 8) || ana_k < p->ana_k_min || (ana_mb != 1 && ana_mb != 2)) {
+        set_error("tiles: synthesis ring pairs per lane 1 or 2, maps per wave 1, 2, 4 or 8; "
+                  "analysis ring pairs per lane 4 (nside <= 256) or 8, maps per wave 1 or 2");
         return DMWF_ERR_INVALID_ARG;
     }
     p->syn_k = syn_k;
     p->syn_mb = syn_mb;
     p->ana_k = ana_k;
+    p->ana_mb = ana_mb;
     p->nchunk_ana = (p->nq + 64 * ana_k - 1) / (64 * ana_k);
     return DMWF_OK;
 }
 
-// Time every synthesis tile on the plan's own shape (all maps, full band,
-// zero input: the instruction stream does not depend on the values) and keep
-// the fastest.  Every tile computes each map's sums in the same order, so the
-// choice changes no result.
+// Time every Legendre tile on the plan's own shape (all maps, full band; the
+// instruction stream does not depend on the values) and keep the fastest.
 dmwf_status dmwf_autotune(dmwf_plan* p, void* ws, size_t ws_bytes, void* stream, int* choice,
                           float* ms_out) {
     if (!p) {
@@ -869,6 +868,8 @@ dmwf_status dmwf_autotune(dmwf_plan* p, void* ws, size_t ws_bytes, void* stream,
     const LegMaps lm{nm, W.ell_full(), 0, nullptr};
     float best = 1e30f;
     int bk = p->syn_k, bmb = p->syn_mb, idx = 0;
+    if (ms_out)
+        for (int i = 8; i < 12; ++i) ms_out[i] = -1.0f;
     dmwf_status res = DMWF_OK;
     for (int k = 1; k <= 2 && res == DMWF_OK; ++k) {
         for (int mb = 1; mb <= 8 && res == DMWF_OK; mb *= 2, ++idx) {
@@ -901,18 +902,21 @@ dmwf_status dmwf_autotune(dmwf_plan* p, void* ws, size_t ws_bytes, void* stream,
     }
     p->syn_k = bk;
     p->syn_mb = bmb;
-    // analysis: ring pairs per lane 8, and 4 where the buffers allow it
+    // analysis: ring pairs per lane 8, and 4 where the buffers allow it;
+    // one or two maps per wave
     float abest = 1e30f;
-    int ak = p->ana_k;
-    for (int k = p->ana_k_min; k <= 8 && res == DMWF_OK; k *= 2) {
+    int ak = p->ana_k, amb = p->ana_mb;
+    for (int t = 0; t < 4 && res == DMWF_OK; ++t) {
+        const int k = t < 2 ? 4 : 8, mb = 1 + (t & 1);
+        if (k < p->ana_k_min || mb > nm) continue;
         p->ana_k = k;
         p->nchunk_ana = (p->nq + 64 * k - 1) / (64 * k);
         const int reps = 3;
-        res = launch_leg_ana(p, W.spec(0), W.part(0), lm, 1, s);
+        res = launch_leg_ana(p, W.spec(0), W.part(0), lm, mb, s);
         if (res != DMWF_OK) break;
         if (hipEventRecord(e0, s) != hipSuccess) res = DMWF_ERR_HIP;
         for (int r = 0; r < reps && res == DMWF_OK; ++r)
-            res = launch_leg_ana(p, W.spec(0), W.part(0), lm, 1, s);
+            res = launch_leg_ana(p, W.spec(0), W.part(0), lm, mb, s);
         float ms = 0.0f;
         if (res == DMWF_OK && (hipEventRecord(e1, s) != hipSuccess ||
                                hipEventSynchronize(e1) != hipSuccess ||
@@ -921,14 +925,15 @@ dmwf_status dmwf_autotune(dmwf_plan* p, void* ws, size_t ws_bytes, void* stream,
             res = DMWF_ERR_HIP;
         }
         ms /= reps;
-        if (ms_out) ms_out[8 + (k == 4 ? 0 : 1)] = ms;
+        if (ms_out) ms_out[8 + t] = ms;
         if (res == DMWF_OK && ms < abest) {
             abest = ms;
             ak = k;
+            amb = mb;
         }
     }
-    if (ms_out && p->ana_k_min > 4) ms_out[8] = -1.0f;
     p->ana_k = ak;
+    p->ana_mb = amb;
     p->nchunk_ana = (p->nq + 64 * ak - 1) / (64 * ak);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -937,6 +942,7 @@ dmwf_status dmwf_autotune(dmwf_plan* p, void* ws, size_t ws_bytes, void* stream,
         choice[0] = bk;
         choice[1] = bmb;
         choice[2] = ak;
+        choice[3] = amb;
     }
     return res;
 }

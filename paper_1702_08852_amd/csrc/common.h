@@ -123,7 +123,7 @@ struct dmwf_plan {
     // Legendre tiles, set by default and by dmwf_autotune.  Synthesis: ring
     // pairs per lane (1 or 2) and maps per wave (1, 2, 4 or 8; the recurrence
     // is computed once for all of them).  Analysis: ring pairs per lane (4 or
-    // 8; nchunk_ana follows), one map per wave.
+    // 8; nchunk_ana follows) and maps per wave (1 or 2).
     int syn_k = 2, syn_mb = 1, ana_mb = 1, ana_k = 8;
     int ana_k_min = 8;  // smallest analysis tile the partial-sum buffer holds
     int lp;        // m-row length of the ring-major F/G buffer, lmax+1 rounded up to 4

@@ -707,17 +707,21 @@ dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const
 
 dmwf_status launch_leg_ana(dmwf_plan* p, const double2* spec, double2* part, const LegMaps& lm,
                            int mb_want, hipStream_t s) {
-    (void)mb_want;
     AnaArgs a{p->d_x,   p->d_ls,        p->d_s0,  p->d_s1, p->d_A,
               spec,     p->ws.spec_map, part,     (size_t)p->nalm + kTablePad,
               p->ws.part_map, lm.ell,   lm.ell_stride, lm.ctrl, p->lmax,
               p->nq,    p->lp,          lm.nm};
     ProfScope ps(p, s, PROF_LEG_ANA);
-    const dim3 grid(p->nchunk_ana * leg_groups8(p), lm.nm);
-    if (p->ana_k == 4)
-        hipLaunchKernelGGL((k_leg_ana<4, 1>), grid, dim3(64 * kLegWaves), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_leg_ana<8, 1>), grid, dim3(64 * kLegWaves), 0, s, a);
+    const int mb = pick_mb(mb_want, lm.nm, 2);
+    const dim3 grid(p->nchunk_ana * leg_groups8(p), (lm.nm + mb - 1) / mb);
+    const dim3 block(64 * kLegWaves);
+    if (p->ana_k == 4) {
+        if (mb == 2) hipLaunchKernelGGL((k_leg_ana<4, 2>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_leg_ana<4, 1>), grid, block, 0, s, a);
+    } else {
+        if (mb == 2) hipLaunchKernelGGL((k_leg_ana<8, 2>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_leg_ana<8, 1>), grid, block, 0, s, a);
+    }
     DMWF_HIP(hipGetLastError());
     return DMWF_OK;
 }

@@ -71,7 +71,7 @@ def load() -> ctypes.CDLL:
     lib.dmwf_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(_Schedule), vp, vp,
                                ctypes.POINTER(_Stats), vp, sz, vp]
     lib.dmwf_autotune.argtypes = [vp, vp, sz, vp, ctypes.POINTER(ci), ctypes.POINTER(ctypes.c_float)]
-    lib.dmwf_set_tiles.argtypes = [vp, ci, ci, ci]
+    lib.dmwf_set_tiles.argtypes = [vp, ci, ci, ci, ci]
     lib.dmwf_wf_residual.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(cd), vp, sz, vp]
     lib.dmwf_profile_enable.argtypes = [vp, ci]
     lib.dmwf_profile_read.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ctypes.c_char_p),
@@ -216,18 +216,19 @@ class Plan:
 
     def autotune(self):
         """Time the Legendre tiles on this plan's shape and keep the fastest.
-        Returns ((synthesis rings per lane, maps per wave, analysis rings per
-        lane), {candidate: ms})."""
-        ch = (ctypes.c_int * 3)()
-        ms = (ctypes.c_float * 10)()
+        Returns ((synthesis rings per lane, synthesis maps per wave, analysis
+        rings per lane, analysis maps per wave), {candidate: ms})."""
+        ch = (ctypes.c_int * 4)()
+        ms = (ctypes.c_float * 12)()
         _check(load().dmwf_autotune(self._h, self.ws.data_ptr(), self.ws_bytes, _stream(), ch, ms),
                "dmwf_autotune")
         times = {f"syn{1 + i // 4}x{1 << (i % 4)}": float(ms[i]) for i in range(8) if ms[i] >= 0.0}
-        times.update({f"ana{k}": float(ms[8 + j]) for j, k in enumerate((4, 8)) if ms[8 + j] >= 0.0})
-        return (int(ch[0]), int(ch[1]), int(ch[2])), times
+        times.update({f"ana{4 if t < 2 else 8}x{1 + (t & 1)}": float(ms[8 + t])
+                      for t in range(4) if ms[8 + t] >= 0.0})
+        return (int(ch[0]), int(ch[1]), int(ch[2]), int(ch[3])), times
 
-    def set_tiles(self, syn_k: int, syn_mb: int, ana_k: int) -> None:
-        _check(load().dmwf_set_tiles(self._h, int(syn_k), int(syn_mb), int(ana_k)),
+    def set_tiles(self, syn_k: int, syn_mb: int, ana_k: int, ana_mb: int = 1) -> None:
+        _check(load().dmwf_set_tiles(self._h, int(syn_k), int(syn_mb), int(ana_k), int(ana_mb)),
                "dmwf_set_tiles")
 
     def wf_residual(self, cl, d, ninv, alm) -> float:

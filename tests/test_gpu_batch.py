@@ -131,9 +131,10 @@ def test_batched_solve_names_the_bad_map():
 
 
 def test_every_legendre_tile_gives_the_same_result():
-    """Every synthesis tile computes each map's sums in the same order: the
-    maps come out bit for bit alike; the analysis tiles differ in the order of
-    the ring-pair sums only (rounding)."""
+    """Every synthesis tile, and the maps per wave of the analysis, compute each
+    map's sums in the same order: the maps come out bit for bit alike; the
+    analysis ring pairs per lane differ in the order of the ring-pair sums only
+    (rounding)."""
     dev = device()
     nside, lmax, nmaps = 16, 32, 5
     a = _stack([inp.random_alm(lmax, 600 + k) for k in range(nmaps)], dev)
@@ -148,23 +149,26 @@ def test_every_legendre_tile_gives_the_same_result():
                 ref_syn = got
             np.testing.assert_array_equal(got, ref_syn)
     for ak in (4, 8):
-        plan.set_tiles(2, 1, ak)
+        plan.set_tiles(2, 1, ak, 1)
         got = plan.adjoint(mp).cpu().numpy()
+        plan.set_tiles(2, 1, ak, 2)
+        np.testing.assert_array_equal(plan.adjoint(mp).cpu().numpy(), got)
         if ref_adj is None:
             ref_adj = got
         assert rel(got, ref_adj) < 1e-14
     for k in range(nmaps):
         ref = oracle.alm2map(a[k].cpu().numpy(), nside, lmax)
         assert rel(ref_syn[k], ref) < 1e-12
-    (sk, smb, ak), times = plan.autotune()
-    assert sk in (1, 2) and smb in (1, 2, 4, 8) and ak in (4, 8)
-    assert "syn2x1" in times and "ana8" in times and "ana4" in times
+    (sk, smb, ak, amb), times = plan.autotune()
+    assert sk in (1, 2) and smb in (1, 2, 4, 8) and ak in (4, 8) and amb in (1, 2)
+    assert "syn2x1" in times and "ana8x1" in times and "ana4x2" in times
     np.testing.assert_array_equal(plan.alm2map(a).cpu().numpy(), ref_syn)
 
 
 def test_set_tiles_rejects_bad_values():
     from paper_1702_08852_amd import DmwfError
     plan = _plan(512, 64, 1)
-    for bad in ((3, 1, 8), (2, 3, 8), (2, 1, 2), (2, 1, 4)):   # 4 per lane needs nside <= 256
+    for bad in ((3, 1, 8, 1), (2, 3, 8, 1), (2, 1, 2, 1), (2, 1, 4, 1),   # 4 per lane needs nside <= 256
+                (2, 1, 8, 4)):
         with pytest.raises(DmwfError):
             plan.set_tiles(*bad)
