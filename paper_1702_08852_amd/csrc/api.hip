@@ -285,18 +285,17 @@ __global__ void k_control(const double* __restrict__ cpart_all, int n, CtrlMaps 
         return;
     }
     const bool advance = c->replay ? c->it_level >= levels[k].replay : ratio < levels[k].eps;
-    if (advance) {
-        if (k + 1 >= c->nlev) {
-            c->status = 0;
-            c->done = 1;
-        } else {
-            ctrl_enter_level(c, levels, k + 1, cm.ell + map, cm.ell_ana + map);
-        }
-        return;
-    }
-    if (c->total >= c->max_iter) {
+    // the last level met: converged, even on the capped iteration; else the
+    // cap stops the map, also on an iteration that would move to the next
+    // level (the host enqueues no iteration beyond the cap)
+    if (advance && k + 1 >= c->nlev) {
+        c->status = 0;
+        c->done = 1;
+    } else if (c->total >= c->max_iter) {
         c->status = 1;
         c->done = 1;
+    } else if (advance) {
+        ctrl_enter_level(c, levels, k + 1, cm.ell + map, cm.ell_ana + map);
     }
 }
 
@@ -1311,17 +1310,26 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
     st = enqueue(nb, cur);
     if (st != DMWF_OK) return st;
     launched += nb;
+    bool whole[2] = {launched >= budget, false};  // snapshot taken after the whole budget
     while (true) {
         batch = std::min(2 * batch, 64);
         nb = (int)std::min<long long>(batch, budget - launched);
         st = enqueue(nb, cur ^ 1);
         if (st != DMWF_OK) return st;
         launched += nb;
+        whole[cur ^ 1] = launched >= budget;
         DMWF_HIP(hipEventSynchronize(p->batch_ev[cur]));
         if (all_done(cur)) {
             DMWF_HIP(hipEventSynchronize(p->batch_ev[cur ^ 1]));
             cur ^= 1;
             break;
+        }
+        if (whole[cur]) {
+            // every map stops within the budget (the cap, or the replayed
+            // counts); a snapshot after it with a map still running is a
+            // control failure, reported instead of waiting forever
+            set_error("solve loop: a map did not stop within its iteration budget");
+            return DMWF_ERR_HIP;
         }
         cur ^= 1;
     }

@@ -172,3 +172,52 @@ def test_set_tiles_rejects_bad_values():
                 (2, 1, 8, 4)):
         with pytest.raises(DmwfError):
             plan.set_tiles(*bad)
+
+
+def test_batched_solve_argument_errors_name_the_map():
+    """A map with every pixel masked, and a replay list that fits some maps'
+    schedules but not another's, are argument errors naming the map; nothing
+    runs."""
+    from paper_1702_08852_amd import DmwfError
+    from paper_1702_08852_amd import dmwf as b
+    dev = device()
+    nside, nmaps = 4, 3
+    ps, T, ds = _members(nside, nmaps)
+    batch = _plan(nside, ps[0].lmax, nmaps)
+    cl, d = _stack([p.cl for p in ps], dev), _stack(ds, dev)
+    w = [p.ninv for p in ps]
+    w_bad = list(w)
+    w_bad[2] = np.zeros_like(w[2])
+    with pytest.raises(DmwfError) as e:
+        batch.solve(cl, d, _stack(w_bad, dev))
+    assert e.value.status == b.ERR_INVALID_ARG and "map 2" in str(e.value)
+    # the maps' schedules differ in length when their alpha differ enough
+    cl2 = [p.cl for p in ps]
+    cl2[1] = cl2[1] * 1e6
+    nlev = [len(dm.level_schedule(dm.alpha_of(w[k]), 1.0 / T.omega, cl2[k], 0.75))
+            for k in range(nmaps)]
+    assert len(set(nlev)) > 1
+    with pytest.raises(DmwfError) as e:
+        batch.solve(_stack(cl2, dev), d, _stack(w, dev), replay=[1] * nlev[0])
+    assert e.value.status == b.ERR_INVALID_ARG and "map" in str(e.value)
+
+
+def test_batched_iteration_cap_stops_every_map():
+    """A cap below every map's need stops each map at the cap; the statuses
+    report it and the outputs hold each map's iterate after that many
+    iterations, as a one-map plan computes it."""
+    from paper_1702_08852_amd import dmwf as b
+    dev = device()
+    nside, nmaps = 8, 3
+    ps, T, ds = _members(nside, nmaps, first=30)
+    lmax = ps[0].lmax
+    batch = _plan(nside, lmax, nmaps)
+    alm, smap, sts = batch.solve(_stack([p.cl for p in ps], dev), _stack(ds, dev),
+                                 _stack([p.ninv for p in ps], dev), eps_final=1e-8, max_iter=17)
+    single = _plan(nside, lmax, 1)
+    for k, p in enumerate(ps):
+        assert sts[k].status == b.ERR_NOT_CONVERGED and sts[k].n_iter == 17
+        a1, s1, st1 = single.solve(to_dev(p.cl, dev), to_dev(ds[k], dev), to_dev(p.ninv, dev),
+                                   eps_final=1e-8, max_iter=17)
+        np.testing.assert_array_equal(alm[k].cpu().numpy(), a1.cpu().numpy())
+        np.testing.assert_array_equal(smap[k].cpu().numpy(), s1.cpu().numpy())

@@ -261,3 +261,30 @@ def test_solve_rejects_schedules_beyond_the_level_table():
     with pytest.raises(DmwfError) as e:
         plan.solve(to_dev(p.cl, dev), to_dev(d, dev), to_dev(w, dev), beta=0.9999)
     assert e.value.status == b.ERR_INVALID_ARG
+
+
+def test_solve_cap_on_a_level_switch_stops():
+    """A cap that falls on the iteration that completes a level stops the
+    solve there (not converged, exactly the cap), instead of entering the next
+    level; likewise with several maps."""
+    from paper_1702_08852_amd import dmwf as b
+    dev = device()
+    nside = 8
+    p, T, d, w = _cfg1(nside)
+    plan = _plan(nside, p.lmax)
+    cl_t, d_t, w_t = to_dev(p.cl, dev), to_dev(d, dev), to_dev(w, dev)
+    _, _, full = plan.solve(cl_t, d_t, w_t, eps_final=1e-8, eps_coarse=1e-4)
+    for nlev in (1, 3):
+        cap = sum(full.iters_per_level[:nlev])
+        _, _, st = plan.solve(cl_t, d_t, w_t, eps_final=1e-8, eps_coarse=1e-4, max_iter=cap)
+        assert st.status == b.ERR_NOT_CONVERGED and st.n_iter == cap
+        assert st.iters_per_level == full.iters_per_level[:nlev]
+    # the last level completed on the capped iteration is a convergence
+    _, _, st = plan.solve(cl_t, d_t, w_t, eps_final=1e-8, eps_coarse=1e-4, max_iter=full.n_iter)
+    assert st.status == b.OK and st.n_iter == full.n_iter
+    two = _plan(nside, p.lmax, nmaps=2)
+    import torch
+    cap = full.iters_per_level[0]
+    _, _, sts = two.solve(torch.stack([cl_t, cl_t]), torch.stack([d_t, d_t]),
+                          torch.stack([w_t, w_t]), eps_final=1e-8, eps_coarse=1e-4, max_iter=cap)
+    assert all(s.status == b.ERR_NOT_CONVERGED and s.n_iter == cap for s in sts)
