@@ -520,6 +520,7 @@ void dmwf_plan_destroy(dmwf_plan* p) {
     if (p->h_ctrl) (void)hipHostFree(p->h_ctrl);
     for (hipEvent_t e : p->batch_ev)
         if (e) (void)hipEventDestroy(e);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     void* bufs[] = {p->d_x, p->d_sint, p->d_nph, p->d_phi0pi, p->d_start_n, p->d_start_s,
                     p->d_A, p->d_g,    p->d_ls,  p->d_s0,     p->d_s1, p->d_lsmin,
                     p->d_mhi_full};
@@ -709,6 +710,7 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
     w.total = off;
     if (hipHostMalloc((void**)&p->h_ctrl, 2 * nm * sizeof(DevCtrl), hipHostMallocDefault) !=
             hipSuccess ||
+        hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&p->batch_ev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->batch_ev[1], hipEventDisableTiming) != hipSuccess) {
         set_error("allocation of the solve-loop host buffer failed");
@@ -1278,12 +1280,52 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
     // enqueues iterations in growing batches with two batches in flight and
     // reads the control blocks once per batch, so the GPU never waits for the
     // host; iterations enqueued after a map's stop do nothing for that map.
-    auto enqueue = [&](int nit, int slot) -> dmwf_status {
-        for (int i = 0; i < nit; ++i) {
+    // Every iteration after the first is the same sequence of launches with
+    // the same arguments: it is captured once into a HIP graph (the ring
+    // stage's side-stream fork and join become graph branches) and replayed,
+    // which takes the per-launch host cost off the loop.  With kernel timing
+    // enabled the iterations are launched one by one (the timing events are
+    // recorded around each launch).
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    struct GraphGuard {
+        hipGraph_t* g;
+        hipGraphExec_t* e;
+        hipStream_t s;
+        ~GraphGuard() {
+            if (*e) {
+                (void)hipStreamSynchronize(s);  // no replay still in flight
+                (void)hipGraphExecDestroy(*e);
+            }
+            if (*g) (void)hipGraphDestroy(*g);
+        }
+    } guard{&graph, &gexec, s};
+    auto one_iteration = [&]() -> dmwf_status {
+        if (first_pix || p->prof) {
             dmwf_status e = iterate_body(p, W, 0, nm, 0.0, 0.0, 0.0, cl_all, d_all, ninv_all, a,
                                          map_all, first_pix, nullptr, nullptr, W.ctrl(0), s);
-            if (e != DMWF_OK) return e;
             first_pix = 0;
+            return e;
+        }
+        if (!gexec) {
+            // captured on the plan's own stream (the caller's may be the null
+            // stream, which cannot be captured), replayed on the caller's
+            hipStream_t cs = p->cap_stream;
+            DMWF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            dmwf_status e = iterate_body(p, W, 0, nm, 0.0, 0.0, 0.0, cl_all, d_all, ninv_all, a,
+                                         map_all, 0, nullptr, nullptr, W.ctrl(0), cs);
+            const hipError_t ce = hipStreamEndCapture(cs, &graph);
+            if (e != DMWF_OK) return e;
+            DMWF_HIP(ce);
+            DMWF_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        }
+        DMWF_HIP(hipGraphLaunch(gexec, s));
+        return DMWF_OK;
+    };
+    auto enqueue = [&](int nit, int slot) -> dmwf_status {
+        for (int i = 0; i < nit; ++i) {
+            dmwf_status e = one_iteration();
+            if (e != DMWF_OK) return e;
         }
         DMWF_HIP(hipMemcpyAsync(p->h_ctrl + (size_t)slot * nm, W.ctrl(0), nm * sizeof(DevCtrl),
                                 hipMemcpyDeviceToHost, s));

@@ -162,6 +162,8 @@ struct dmwf_plan {
     // solve loop (two batches in flight)
     dmwf::DevCtrl* h_ctrl = nullptr;
     hipEvent_t batch_ev[2] = {nullptr, nullptr};
+    // stream (default priority) on which the solve loop captures its iteration
+    hipStream_t cap_stream = nullptr;
     // profiling
     bool prof = false;
     std::vector<dmwf::ProfEvent> events;

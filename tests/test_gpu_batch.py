@@ -221,3 +221,28 @@ def test_batched_iteration_cap_stops_every_map():
                                    eps_final=1e-8, max_iter=17)
         np.testing.assert_array_equal(alm[k].cpu().numpy(), a1.cpu().numpy())
         np.testing.assert_array_equal(smap[k].cpu().numpy(), s1.cpu().numpy())
+
+
+def test_graph_replays_equal_launch_by_launch_iterations():
+    """The solve loop replays one captured iteration as a HIP graph; with
+    kernel timing on it launches every kernel itself.  Both give the same bits,
+    for one map and for a batch, and the graph path gives them again on a
+    second solve (thousands of replays, host synchronisations in between)."""
+    dev = device()
+    nside, nmaps = 8, 3
+    ps, T, ds = _members(nside, nmaps, first=40)
+    lmax = ps[0].lmax
+    args = (_stack([p.cl for p in ps], dev), _stack(ds, dev), _stack([p.ninv for p in ps], dev))
+    for plan, sel in ((_plan(nside, lmax, nmaps), slice(None)), (_plan(nside, lmax, 1), 0)):
+        a_in = tuple(x[sel].contiguous() for x in args)
+        plan.profile(True)
+        a_e, s_e, st_e = plan.solve(*a_in, eps_final=1e-8)
+        plan.profile_read()
+        plan.profile(False)
+        a_g, s_g, st_g = plan.solve(*a_in, eps_final=1e-8)
+        a_g2, s_g2, _ = plan.solve(*a_in, eps_final=1e-8)
+        for x, y in ((a_e, a_g), (s_e, s_g), (a_g, a_g2), (s_g, s_g2)):
+            np.testing.assert_array_equal(x.cpu().numpy(), y.cpu().numpy())
+        st_e = st_e if isinstance(st_e, list) else [st_e]
+        st_g = st_g if isinstance(st_g, list) else [st_g]
+        assert [s.iters_per_level for s in st_e] == [s.iters_per_level for s in st_g]
