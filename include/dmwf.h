@@ -147,6 +147,8 @@ dmwf_status dmwf_dm_iterate(dmwf_plan* plan, double xi, double alpha, const doub
  * level decisions (Cauchy ratio against each level's tolerance, the next xi,
  * the stop) are taken on the device after every iteration; the host enqueues
  * iterations in batches and synchronises with the stream once per batch.
+ * Iterations after the first are replays of one HIP graph of the iteration
+ * (launch by launch while kernel timing is enabled; both give the same bits).
  * The maps of the plan iterate together, one launch per stage for all of
  * them, each with its own alpha, schedule, level and stop; a map that has
  * stopped is left untouched while the others go on.  Every map comes out
