@@ -10,7 +10,10 @@ before the timed region.
 Prints one JSON line.  Besides solves/s it reports the full-band transform pair
 rate (one iteration at xi = alpha, l_iter = lmax), the roofline position of
 the dominant kernel measured with HIP events around each of its launches on
-the launch stream, and the CPU oracle on a bounded sample.
+the launch stream, and the CPU oracle on a bounded sample.  Further records:
+the solves and pair rates of configurations 1 and 2 (Nside 16 and 256) with
+the oracle beside them, and the batched workload (96 maps of Nside 128, 256
+and 512, each Nside group solved by one plan).
 """
 from __future__ import annotations
 
@@ -231,6 +234,72 @@ def batch_group(nside, dev, pairs):
     }
 
 
+def bench_configs(dev, with_cpu):
+    """Configurations 1 and 2 (Nside 16, lmax 32, eps 1e-8; Nside 256, lmax 512,
+    eps 1e-6): one full solve each as a user runs it (graph replays, no kernel
+    timing) and the full-band pair rate, with the oracle beside them: the full
+    oracle solve at Nside 16, one oracle pair times the GPU's iteration count
+    at Nside 256 (extrapolated)."""
+    import numpy as np
+    import torch
+
+    import dmwf_inputs as inp
+    import oracle
+    from oracle import dm
+    from paper_1702_08852_amd import Plan
+
+    out = {}
+    for name in ("cfg1", "cfg2"):
+        p = inp.make_problem(name)
+        nside, lmax = p.nside, p.lmax
+        plan = Plan(nside, lmax, device=dev)
+        sig = plan.alm2map(torch.tensor(p.alm_true, device=dev))
+        d = (sig + torch.tensor(p.sigma * p.white, device=dev)).masked_fill(
+            torch.tensor(p.mask, device=dev), 0.0).contiguous()
+        w = torch.tensor(p.ninv, device=dev)
+        cl = torch.tensor(p.cl, device=dev)
+        plan.solve(cl, d, w, eps_final=p.eps_final, max_iter=20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        alm, _, st = plan.solve(cl, d, w, eps_final=p.eps_final, eps_coarse=1e-4)
+        torch.cuda.synchronize()
+        solve_s = time.perf_counter() - t0
+
+        def run(n):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            plan.solve(cl, d, w, eps_final=p.eps_final, start_final=True, alm=alm.clone(),
+                       replay=[n])
+            torch.cuda.synchronize()
+            return time.perf_counter() - t
+
+        run(5)
+        pair_ms = (run(205) - run(5)) / 200 * 1e3
+        rec = {"nside": nside, "lmax": lmax, "eps_final": p.eps_final, "solve_s": solve_s,
+               "iterations": st.n_iter, "levels": st.n_levels,
+               "wf_residual": plan.wf_residual(cl, d, w, alm), "ms_per_pair": pair_ms,
+               "pairs_per_s": 1e3 / pair_ms}
+        if with_cpu:
+            T = oracle.SphereTransforms(nside, lmax)
+            dh, wh = d.cpu().numpy(), w.cpu().numpy()
+            if name == "cfg1":
+                t0 = time.perf_counter()
+                ref = dm.solve(T, dh, wh, p.cl, eps_final=p.eps_final, eps_coarse=1e-4)
+                cpu_s = time.perf_counter() - t0
+                rec["cpu_oracle"] = {"solve_s": cpu_s, "iterations": ref.n_iter,
+                                     "kind": "full oracle solve", "cores": oracle.max_threads()}
+            else:
+                t0 = time.perf_counter()
+                T.adjoint(T.synth(p.alm_true))
+                pair_s = time.perf_counter() - t0
+                rec["cpu_oracle"] = {"solve_s": pair_s * st.n_iter, "pair_s": pair_s,
+                                     "kind": "one oracle pair times the GPU iteration count "
+                                             "(extrapolated)", "cores": oracle.max_threads()}
+        out[name] = rec
+        del plan
+    return out
+
+
 def bench_batch(dev, pairs):
     """The batched workload: 96 maps of Nside {128: 48, 256: 32, 512: 16}, lmax
     2 Nside, each with its own mask and noise, every group solved as one batch."""
@@ -441,9 +510,10 @@ def main():
                   "iters_per_level": st.iters_per_level, "lmax_per_level": st.lmax_per_level,
                   "kernel_ms_per_solve": {k: v[1] / args.steps for k, v in prof.items() if v[0]}},
     }
+    del plan
+    torch.cuda.empty_cache()
+    out["configs"] = bench_configs(dev, not args.no_cpu)
     if not args.no_batch:
-        del plan
-        torch.cuda.empty_cache()
         out["batched"] = bench_batch(dev, 20)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(nside, lmax, iters, args.cpu_fraction)
