@@ -225,8 +225,8 @@ def test_solve_iteration_cap_inside_a_level():
 
 
 def test_solve_two_maps_match_single_map_solves():
-    """A plan with two maps solves them one after the other, each exactly as a
-    single-map plan would."""
+    """A plan with two maps (of different spectra, noise and masks) solves them
+    together, each exactly as a single-map plan would."""
     import torch
     dev = device()
     nside = 8
