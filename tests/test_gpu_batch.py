@@ -250,3 +250,37 @@ def test_graph_replays_equal_launch_by_launch_iterations():
         st_e = st_e if isinstance(st_e, list) else [st_e]
         st_g = st_g if isinstance(st_g, list) else [st_g]
         assert [s.iters_per_level for s in st_e] == [s.iters_per_level for s in st_g]
+
+
+def test_plans_solving_at_once_from_threads():
+    """Plans of different Nside solving at the same time, each on its own
+    stream from its own host thread (the batched workload's groups), give the
+    bits each gives alone."""
+    import threading
+    import torch
+    dev = device()
+    jobs = []
+    for nside, nmaps, first in ((4, 3, 50), (8, 2, 60)):
+        ps, T, ds = _members(nside, nmaps, first=first)
+        plan = _plan(nside, ps[0].lmax, nmaps)
+        args = (_stack([p.cl for p in ps], dev), _stack(ds, dev), _stack([p.ninv for p in ps], dev))
+        alone = plan.solve(*args, eps_final=1e-8)
+        jobs.append((plan, args, alone))
+    torch.cuda.synchronize()
+    out = [None] * len(jobs)
+    streams = [torch.cuda.Stream(device=dev) for _ in jobs]
+
+    def run(i):
+        plan, args, _ = jobs[i]
+        with torch.cuda.stream(streams[i]):
+            out[i] = plan.solve(*args, eps_final=1e-8)
+        streams[i].synchronize()
+
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(len(jobs))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    for (plan, args, alone), got in zip(jobs, out):
+        np.testing.assert_array_equal(got[0].cpu().numpy(), alone[0].cpu().numpy())
+        np.testing.assert_array_equal(got[1].cpu().numpy(), alone[1].cpu().numpy())
