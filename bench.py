@@ -363,6 +363,8 @@ def main():
                     help="fraction of rings (synthesis) and of m (adjoint) the oracle evaluates")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 96-map workload")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip configurations 1 and 2 (Nside 16 and 256)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only run the batched workload and print its record")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -548,7 +550,8 @@ def main():
     }
     del plan
     torch.cuda.empty_cache()
-    out["configs"] = bench_configs(dev, not args.no_cpu)
+    if not args.no_configs:
+        out["configs"] = bench_configs(dev, not args.no_cpu)
     if not args.no_batch:
         out["batched"] = bench_batch(dev, 20)
     if not args.no_cpu:
