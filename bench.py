@@ -362,7 +362,8 @@ def main():
     ap.add_argument("--cpu-fraction", type=float, default=1.0,
                     help="fraction of rings (synthesis) and of m (adjoint) the oracle evaluates")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched 96-map workload")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched measurements (96-map workload, four-map pair rate)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip configurations 1 and 2 (Nside 16 and 256)")
     ap.add_argument("--batch-only", action="store_true",
@@ -487,29 +488,33 @@ def main():
     resid = plan.wf_residual(cl, d, w, alm)
     iters = st.n_iter
 
-    # the same full-band iteration for four copies of this map in one plan
-    # (one launch per stage for all four, autotuned tiles)
-    from paper_1702_08852_amd import Plan
-    nb = 4
-    bplan = Plan(nside, lmax, nmaps=nb, device=dev)
-    btile, _ = bplan.autotune()
-    bcl, bd, bw = (x.unsqueeze(0).repeat(nb, *([1] * x.dim())).contiguous() for x in (cl, d, w))
-    balm = alm.unsqueeze(0).repeat(nb, 1, 1).contiguous()
+    batched4 = None
+    if not args.no_batch:
+        # the same full-band iteration for four copies of this map in one plan
+        # (one launch per stage for all four, autotuned tiles)
+        from paper_1702_08852_amd import Plan
+        nb = 4
+        bplan = Plan(nside, lmax, nmaps=nb, device=dev)
+        btile, _ = bplan.autotune()
+        bcl, bd, bw = (x.unsqueeze(0).repeat(nb, *([1] * x.dim())).contiguous() for x in (cl, d, w))
+        balm = alm.unsqueeze(0).repeat(nb, 1, 1).contiguous()
 
-    def breplay(n):
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        bplan.solve(bcl, bd, bw, eps_final=eps_final, start_final=True, alm=balm.clone(),
-                    replay=[n])
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1)
+        def breplay(n):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            bplan.solve(bcl, bd, bw, eps_final=eps_final, start_final=True, alm=balm.clone(),
+                        replay=[n])
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1)
 
-    breplay(5)
-    b_it_ms = (breplay(5 + 20) - breplay(5)) / 20
-    del bplan, bcl, bd, bw, balm
-    torch.cuda.empty_cache()
+        breplay(5)
+        b_it_ms = (breplay(5 + 20) - breplay(5)) / 20
+        batched4 = {"ms_per_iteration": b_it_ms, "ms_per_map_pair": b_it_ms / nb,
+                    "gain_per_map": pair_ms / (b_it_ms / nb), "tiles": list(btile)}
+        del bplan, bcl, bd, bw, balm
+        torch.cuda.empty_cache()
     out = {
         "metric": METRIC,
         "value": 1e3 / ms_per_step,
@@ -540,9 +545,7 @@ def main():
                                      f"graph replays; kernel split from the same replays "
                                      f"launched one by one with kernel timing"),
                      "dm_iterate_call_ms": dm_iterate_ms,
-                     "batched_4_maps": {"ms_per_iteration": b_it_ms, "ms_per_map_pair": b_it_ms / nb,
-                                        "gain_per_map": pair_ms / (b_it_ms / nb),
-                                        "tiles": list(btile)}},
+                     "batched_4_maps": batched4},
         "solve": {"iterations": iters, "levels": st.n_levels, "alpha": st.alpha,
                   "final_cauchy": st.final_cauchy, "wf_residual": resid,
                   "iters_per_level": st.iters_per_level, "lmax_per_level": st.lmax_per_level,
