@@ -19,10 +19,12 @@
 // values mu_{l-1}, mu_l there, computed with exponent rescaling; the kernels
 // start each ring at that l and treat the terms before it as zero.
 //
-// Mapping: one wave per (m, chunk of 64*K ring pairs); lane = ring pair, each
-// lane carries K ring pairs spaced 64 apart.  The recurrence runs in l inside
-// a lane, so the synthesis sum over l needs no communication; the analysis sum
-// over rings is reduced across lanes through LDS once per block of 16 l.
+// Mapping: one wave per (m, chunk of 64*K ring pairs, group of MB maps);
+// lane = ring pair, each lane carries K ring pairs spaced 64 apart.  The
+// recurrence runs in l inside a lane and is shared by the wave's MB maps
+// (only the contraction FMAs are per map), so the synthesis sum over l needs
+// no communication; the analysis sum over rings is reduced across lanes
+// through LDS once per block of 16 l.  K and MB are per-plan tiles.
 #include <climits>
 
 #include "common.h"
