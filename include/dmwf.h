@@ -190,7 +190,8 @@ dmwf_status dmwf_set_tiles(dmwf_plan* plan, int syn_k, int syn_mb, int ana_k, in
 
 /* ||A x - y|| / ||y|| with A = 1 + C^1/2 Y^H W Y C^1/2, x = C^-1/2 a,
  * y = C^1/2 Y^H W d over modes with C_l > 0 (paper Section 4, Appendix C),
- * norms on a_lm counting m > 0 twice.  Map 0; synchronises the stream. */
+ * norms on a_lm counting m > 0 twice, for every map of the plan: host_out
+ * receives nmaps values.  Synchronises the stream. */
 dmwf_status dmwf_wf_residual(dmwf_plan* plan, const double* dev_cl, const double* dev_d,
                              const double* dev_ninv, const double* dev_alm, double* host_out,
                              void* dev_ws, size_t ws_bytes, void* stream);

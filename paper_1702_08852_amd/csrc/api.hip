@@ -1102,8 +1102,14 @@ dmwf_status dmwf_wf_residual(dmwf_plan* p, const double* cl, const double* d, co
     Ws W;
     dmwf_status st = check_ws(p, ws, ws_bytes, &W);
     if (st != DMWF_OK) return st;
-    return residual_map(p, W, cl, d, ninv, reinterpret_cast<const double2*>(alm), host_out,
-                        static_cast<hipStream_t>(stream));
+    for (int k = 0; k < p->nmaps; ++k) {
+        st = residual_map(p, W, cl + (size_t)k * (p->lmax + 1), d + (size_t)k * p->npix,
+                          ninv + (size_t)k * p->npix,
+                          reinterpret_cast<const double2*>(alm) + (size_t)k * p->nalm,
+                          host_out + k, static_cast<hipStream_t>(stream));
+        if (st != DMWF_OK) return st;
+    }
+    return DMWF_OK;
 }
 
 dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,

@@ -231,12 +231,15 @@ class Plan:
         _check(load().dmwf_set_tiles(self._h, int(syn_k), int(syn_mb), int(ana_k), int(ana_mb)),
                "dmwf_set_tiles")
 
-    def wf_residual(self, cl, d, ninv, alm) -> float:
-        out = ctypes.c_double()
+    def wf_residual(self, cl, d, ninv, alm):
+        """FP64 residual of the Wiener filter system: a float for a one-map
+        plan, a list of nmaps floats otherwise."""
+        out = (ctypes.c_double * self.nmaps)()
         _check(load().dmwf_wf_residual(self._h, _ptr(cl), _ptr(d), _ptr(ninv), _ptr(alm),
-                                       ctypes.byref(out), self.ws.data_ptr(), self.ws_bytes,
+                                       out, self.ws.data_ptr(), self.ws_bytes,
                                        _stream()), "dmwf_wf_residual")
-        return float(out.value)
+        vals = [float(v) for v in out]
+        return vals[0] if self.nmaps == 1 else vals
 
     def profile(self, enable: bool = True) -> None:
         _check(load().dmwf_profile_enable(self._h, int(bool(enable))), "dmwf_profile_enable")

@@ -32,6 +32,11 @@ def _stack(arrs, dev):
     return torch.tensor(np.stack(arrs), device=dev)
 
 
+def torch_tensor(a, dev):
+    import torch
+    return torch.tensor(a, device=dev)
+
+
 def _plan(nside, lmax, nmaps):
     from paper_1702_08852_amd import Plan
     return Plan(nside, lmax, nmaps=nmaps, device=device())
@@ -80,6 +85,10 @@ def test_batched_solve_matches_oracle_per_map():
         assert rel(smap[k], ref.map) < 1e-10
         assert sts[k].wf_residual == pytest.approx(
             dm.wf_residual(T, ref.alm, ds[k], p.ninv, p.cl), rel=1e-6)
+    # the residual entry point gives every map's, as the solve reported them
+    res = batch.wf_residual(_stack([p.cl for p in ps], dev), _stack(ds, dev),
+                            _stack([p.ninv for p in ps], dev), torch_tensor(alm, dev))
+    assert res == [s.wf_residual for s in sts]
 
 
 def test_batched_warm_start_equals_single_map():
