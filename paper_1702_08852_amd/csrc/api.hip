@@ -26,7 +26,6 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // ---------------------------------------------------------------------------
 __global__ void k_set_int(int* p, int v) { *p = v; }
 
-// Largest l with C_l - mu > 0 (the Heaviside truncation of S_bar), or -1.
 // Level set-up of one iteration call in a single launch: every block finds
 // l_iter = max{l : C_l > mu} itself; block 0 stores it and sets the analysis
 // band of the ring stage to lmax; each thread then finds the m bound of one
@@ -50,35 +49,7 @@ __global__ void k_level(const double* __restrict__ cl, int lmax, double mu,
     }
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nq) return;
-    const int* row = lsmin + (size_t)q * (lmax + 1);
-    int hi = min(ell, lmax);
-    if (hi < 0 || row[0] > ell) {
-        mhi[q] = -1;
-        return;
-    }
-    int lo = 0;  // row[lo] <= ell
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (row[mid] <= ell) lo = mid;
-        else hi = mid - 1;
-    }
-    mhi[q] = lo;
-}
-
-__global__ void k_ell_from_cl(const double* __restrict__ cl, int lmax, double mu, int* out) {
-    int best = -1;
-    for (int l = threadIdx.x; l <= lmax; l += blockDim.x)
-        if (cl[l] - mu > 0.0) best = l;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o));
-    __shared__ int w[4];
-    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int b = w[0];
-        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) b = max(b, w[i]);
-        *out = b;
-    }
+    mhi[q] = m_bound(lsmin + (size_t)q * (lmax + 1), ell, lmax);
 }
 
 // a'_lm = g_lm a_lm (synthesis input), Im a_l0 dropped.  grid (l blocks, m,
@@ -192,20 +163,7 @@ __global__ void k_level_tab(const int* __restrict__ lsmin, int nq, int lmax,
     levels += (size_t)map * kMaxLevels;
     mhi_tab += (size_t)map * kMaxLevels * nq;
     const int k = (int)(i / nq), q = (int)(i % nq);
-    const int ell = levels[k].ell;
-    const int* row = lsmin + (size_t)q * (lmax + 1);
-    int hi = min(ell, lmax);
-    if (hi < 0 || row[0] > ell) {
-        mhi_tab[i] = -1;
-        return;
-    }
-    int lo = 0;  // row[lo] <= ell
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (row[mid] <= ell) lo = mid;
-        else hi = mid - 1;
-    }
-    mhi_tab[i] = lo;
+    mhi_tab[i] = m_bound(lsmin + (size_t)q * (lmax + 1), levels[k].ell, lmax);
 }
 
 __device__ void ctrl_enter_level(DevCtrl* c, const DevLevel* levels, int k, int* ell_out,

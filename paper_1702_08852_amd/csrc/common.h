@@ -219,6 +219,21 @@ struct ProfScope {
     }
 };
 
+// Largest m <= ell whose suffix-minimum recurrence start row[m] is <= ell, or
+// -1 if none: beyond it every lambda_lm of the ring pair lies past the band
+// limit.  row = lsmin of one ring pair, non-decreasing in m (binary search).
+__device__ inline int m_bound(const int* row, int ell, int lmax) {
+    int hi = ell < lmax ? ell : lmax;
+    if (hi < 0 || row[0] > ell) return -1;
+    int lo = 0;  // row[lo] <= ell
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row[mid] <= ell) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 __host__ __device__ inline long long alm_base(int m, int lmax) {
     // slot of (l, m) is alm_base(m) + l
     return (long long)m * (2LL * lmax + 1 - m) / 2;
@@ -281,8 +296,6 @@ struct RingMaps {
 };
 dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const RingMaps& rm,
                         const RingIO& io, hipStream_t s);
-// mhi[q] = largest m <= *ell_dev whose recurrence start is <= *ell_dev (-1 if none).
-dmwf_status launch_mhi(dmwf_plan* p, const int* ell_dev, int* mhi, hipStream_t s);
 // Ring transform tables and launch classes; called by dmwf_plan_create.
 dmwf_status build_ring_tables(dmwf_plan* p);
 void free_ring_tables(dmwf_plan* p);

@@ -134,27 +134,13 @@ __global__ void k_lsmin(int lmax, int nq, const int* __restrict__ ls, int* __res
     }
 }
 
-// mhi[q] = largest m <= ell with lsmin[q][m] <= ell, or -1.  Every m above it
-// has every start beyond ell, so its lambda_lm are all skipped at this band
-// limit.  Binary search on the non-decreasing lsmin.
-__global__ void k_mhi(int lmax, int nq, const int* __restrict__ lsmin, const int* ell_dev,
-                      int ell_val, int* __restrict__ mhi) {
+// mhi[q] = m_bound of ring pair q at band limit ell (every m above it has
+// every start beyond ell, so its lambda_lm are all skipped).
+__global__ void k_mhi(int lmax, int nq, const int* __restrict__ lsmin, int ell,
+                      int* __restrict__ mhi) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nq) return;
-    const int ell = ell_dev ? *ell_dev : ell_val;
-    const int* row = lsmin + (size_t)q * (lmax + 1);
-    int hi = min(ell, lmax);
-    if (hi < 0 || row[0] > ell) {
-        mhi[q] = -1;
-        return;
-    }
-    int lo = 0;  // row[lo] <= ell
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (row[mid] <= ell) lo = mid;
-        else hi = mid - 1;
-    }
-    mhi[q] = lo;
+    mhi[q] = m_bound(lsmin + (size_t)q * (lmax + 1), ell, lmax);
 }
 
 // Workgroup b of a 1-D grid runs on XCD b mod 8 (round-robin dispatch).  Give
@@ -642,19 +628,11 @@ dmwf_status launch_seeds(dmwf_plan* p, hipStream_t s) {
     hipLaunchKernelGGL(k_lsmin, dim3((p->nq + 63) / 64), dim3(64), 0, s, p->lmax, p->nq, p->d_ls,
                        p->d_lsmin);
     hipLaunchKernelGGL(k_mhi, dim3((p->nq + 63) / 64), dim3(64), 0, s, p->lmax, p->nq, p->d_lsmin,
-                       nullptr, p->lmax, p->d_mhi_full);
+                       p->lmax, p->d_mhi_full);
     DMWF_HIP(hipGetLastError());
     DMWF_HIP(hipStreamSynchronize(s));
     DMWF_HIP(hipFree(mant));
     DMWF_HIP(hipFree(expo));
-    return DMWF_OK;
-}
-
-dmwf_status launch_mhi(dmwf_plan* p, const int* ell_dev, int* mhi, hipStream_t s) {
-    ProfScope ps(p, s, PROF_MISC);
-    hipLaunchKernelGGL(k_mhi, dim3((p->nq + 63) / 64), dim3(64), 0, s, p->lmax, p->nq, p->d_lsmin,
-                       ell_dev, 0, mhi);
-    DMWF_HIP(hipGetLastError());
     return DMWF_OK;
 }
 
