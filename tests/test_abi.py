@@ -47,3 +47,18 @@ def test_host_side_validation_without_gpu():
         assert lib.dmwf_plan_create(ctypes.byref(desc), ctypes.byref(h)) == want
         assert not h.value
     assert lib.dmwf_plan_create(None, ctypes.byref(h)) == 1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libdmwf.so not built")
+def test_null_plans_are_argument_errors():
+    """Every entry point taking a plan rejects NULL before touching a device."""
+    from paper_1702_08852_amd import dmwf as b
+    lib = b.load()
+    assert lib.dmwf_set_tiles(None, 2, 1, 8, 1) == b.ERR_INVALID_ARG
+    assert lib.dmwf_autotune(None, None, 0, None, None, None) == b.ERR_INVALID_ARG
+    nb = ctypes.c_size_t()
+    assert lib.dmwf_workspace_bytes(None, ctypes.byref(nb)) == b.ERR_INVALID_ARG
+    assert lib.dmwf_alm2map(None, None, None, None, 0, None) == b.ERR_INVALID_ARG
+    assert lib.dmwf_adjoint(None, None, None, 0, None, 0, None) == b.ERR_INVALID_ARG
+    assert lib.dmwf_profile_enable(None, 1) == b.ERR_INVALID_ARG
+    lib.dmwf_plan_destroy(None)  # accepted
