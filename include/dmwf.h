@@ -148,7 +148,7 @@ dmwf_status dmwf_dm_iterate(dmwf_plan* plan, double xi, double alpha, const doub
  * the stop) are taken on the device after every iteration; the host enqueues
  * iterations in batches and synchronises with the stream once per batch.
  * Iterations after the first are replays of one HIP graph of the iteration
- * (launch by launch while kernel timing is enabled; both give the same bits).
+ * (launch by launch while every launch is timed; all paths give the same bits).
  * The maps of the plan iterate together, one launch per stage for all of
  * them, each with its own alpha, schedule, level and stop; a map that has
  * stopped is left untouched while the others go on.  Every map comes out
@@ -196,10 +196,15 @@ dmwf_status dmwf_wf_residual(dmwf_plan* plan, const double* dev_cl, const double
                              const double* dev_ninv, const double* dev_alm, double* host_out,
                              void* dev_ws, size_t ws_bytes, void* stream);
 
-/* Kernel timing: when enabled, every launch is bracketed by HIP events on the
- * launch stream.  dmwf_profile_read returns, for each kernel class, the launch
- * count and the summed device time in milliseconds (it synchronises the
- * recorded events) and clears the record.  names[i] is a static string. */
+/* Kernel timing.  enable = 1: every launch is bracketed by HIP events on the
+ * launch stream (the solve loop then launches every iteration kernel by
+ * kernel).  enable = 2: only the Legendre analysis launches are (the solve
+ * loop launches the analysis between its events and replays the rest of each
+ * iteration from its graph).  0 switches timing off; other values are
+ * DMWF_ERR_INVALID_ARG.  dmwf_profile_read returns, for each kernel class,
+ * the launch count and the summed device time in milliseconds (it
+ * synchronises the recorded events) and clears the record.  names[i] is a
+ * static string. */
 #define DMWF_NPROF 16
 dmwf_status dmwf_profile_enable(dmwf_plan* plan, int enable);
 dmwf_status dmwf_profile_read(dmwf_plan* plan, int* n_classes, const char** names,

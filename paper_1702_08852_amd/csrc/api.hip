@@ -694,7 +694,8 @@ dmwf_status dmwf_workspace_bytes(const dmwf_plan* p, size_t* bytes) {
 
 dmwf_status dmwf_profile_enable(dmwf_plan* p, int enable) {
     if (!p) return DMWF_ERR_INVALID_ARG;
-    p->prof = enable != 0;
+    if (enable < 0 || enable > 2) return DMWF_ERR_INVALID_ARG;
+    p->prof = enable;
     return DMWF_OK;
 }
 
@@ -816,8 +817,8 @@ dmwf_status dmwf_autotune(dmwf_plan* p, void* ws, size_t ws_bytes, void* stream,
     if (st != DMWF_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int nm = p->nmaps;
-    const bool prof = p->prof;
-    p->prof = false;
+    const int prof = p->prof;
+    p->prof = 0;
     hipLaunchKernelGGL(k_zero2, dim3(256), dim3(256), 0, s, W.ap(0), (long long)nm * p->ws.alm_map);
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, W.ell_full(), p->lmax);
     DMWF_HIP(hipGetLastError());
@@ -917,13 +918,19 @@ namespace {
 // workspace, synthesis, pixel step.  cl, d, w, a and s_map point at map k0's
 // slices.  The solve loop ends the iteration with each map's level decision;
 // dmwf_dm_iterate sums the Cauchy partials into cauchy_out.
-dmwf_status iterate_body(dmwf_plan* p, const Ws& W, int k0, int nm, double xi, double alpha,
+// The iteration's first launch, the Legendre analysis of the residual spectrum.
+dmwf_status iterate_ana(dmwf_plan* p, const Ws& W, int k0, int nm, DevCtrl* ctrl, hipStream_t s) {
+    return launch_leg_ana(p, W.spec(k0), W.part(k0), LegMaps{nm, W.ell(k0), 1, ctrl}, p->ana_mb,
+                          s);
+}
+
+// The rest of the iteration after the analysis.
+dmwf_status iterate_rest(dmwf_plan* p, const Ws& W, int k0, int nm, double xi, double alpha,
                          double mu, const double* cl, const double* d, const double* w,
                          double2* a, double* s_map, int first_pix, const int* mhi_ana,
                          double* cauchy_out, DevCtrl* ctrl, hipStream_t s) {
     const LegMaps lm{nm, W.ell(k0), 1, ctrl};
-    dmwf_status st = launch_leg_ana(p, W.spec(k0), W.part(k0), lm, p->ana_mb, s);
-    if (st != DMWF_OK) return st;
+    dmwf_status st;
     {
         ProfScope ps(p, s, PROF_DIAG);
         DiagArgs da{a,       p->nalm, W.ap(k0), p->ws.alm_map, W.part(k0), p->ws.part_map,
@@ -959,6 +966,16 @@ dmwf_status iterate_body(dmwf_plan* p, const Ws& W, int k0, int nm, double xi, d
     }
     DMWF_HIP(hipGetLastError());
     return DMWF_OK;
+}
+
+dmwf_status iterate_body(dmwf_plan* p, const Ws& W, int k0, int nm, double xi, double alpha,
+                         double mu, const double* cl, const double* d, const double* w,
+                         double2* a, double* s_map, int first_pix, const int* mhi_ana,
+                         double* cauchy_out, DevCtrl* ctrl, hipStream_t s) {
+    dmwf_status st = iterate_ana(p, W, k0, nm, ctrl, s);
+    if (st != DMWF_OK) return st;
+    return iterate_rest(p, W, k0, nm, xi, alpha, mu, cl, d, w, a, s_map, first_pix, mhi_ana,
+                        cauchy_out, ctrl, s);
 }
 
 // ||A x - y|| / ||y|| of one map (its C_l, d, N^-1, a); the workspace slices
@@ -1247,9 +1264,11 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
     // Every iteration after the first is the same sequence of launches with
     // the same arguments: it is captured once into a HIP graph (the ring
     // stage's side-stream fork and join become graph branches) and replayed,
-    // which takes the per-launch host cost off the loop.  With kernel timing
-    // enabled the iterations are launched one by one (the timing events are
-    // recorded around each launch).
+    // which takes the per-launch host cost off the loop.  Timing events are
+    // not recorded by graph replays: with every launch timed (profiling level
+    // 1) the iterations are launched one by one; with the analysis timed
+    // (level 2) it is launched between its events and the rest of the
+    // iteration is replayed from a graph.
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     struct GraphGuard {
@@ -1264,8 +1283,9 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
             if (*g) (void)hipGraphDestroy(*g);
         }
     } guard{&graph, &gexec, s};
+    const bool split = p->prof == 2;
     auto one_iteration = [&]() -> dmwf_status {
-        if (first_pix || p->prof) {
+        if (first_pix || p->prof == 1) {
             dmwf_status e = iterate_body(p, W, 0, nm, 0.0, 0.0, 0.0, cl_all, d_all, ninv_all, a,
                                          map_all, first_pix, nullptr, nullptr, W.ctrl(0), s);
             first_pix = 0;
@@ -1276,12 +1296,19 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
             // stream, which cannot be captured), replayed on the caller's
             hipStream_t cs = p->cap_stream;
             DMWF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            dmwf_status e = iterate_body(p, W, 0, nm, 0.0, 0.0, 0.0, cl_all, d_all, ninv_all, a,
-                                         map_all, 0, nullptr, nullptr, W.ctrl(0), cs);
+            dmwf_status e =
+                split ? iterate_rest(p, W, 0, nm, 0.0, 0.0, 0.0, cl_all, d_all, ninv_all, a,
+                                     map_all, 0, nullptr, nullptr, W.ctrl(0), cs)
+                      : iterate_body(p, W, 0, nm, 0.0, 0.0, 0.0, cl_all, d_all, ninv_all, a,
+                                     map_all, 0, nullptr, nullptr, W.ctrl(0), cs);
             const hipError_t ce = hipStreamEndCapture(cs, &graph);
             if (e != DMWF_OK) return e;
             DMWF_HIP(ce);
             DMWF_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        }
+        if (split) {
+            dmwf_status e = iterate_ana(p, W, 0, nm, W.ctrl(0), s);
+            if (e != DMWF_OK) return e;
         }
         DMWF_HIP(hipGraphLaunch(gexec, s));
         return DMWF_OK;

@@ -165,7 +165,7 @@ struct dmwf_plan {
     // stream (default priority) on which the solve loop captures its iteration
     hipStream_t cap_stream = nullptr;
     // profiling
-    bool prof = false;
+    int prof = 0;  // 0 off, 1 every launch, 2 the Legendre analysis launches only
     std::vector<dmwf::ProfEvent> events;
     std::vector<hipEvent_t> event_pool;  // recorded events are returned here on read
     dmwf::RingGeom geom() const {
@@ -204,15 +204,17 @@ struct ProfScope {
     hipStream_t s;
     int cls;
     hipEvent_t a = nullptr, b = nullptr;
-    ProfScope(dmwf_plan* p_, hipStream_t s_, int c_) : p(p_), s(s_), cls(c_) {
-        if (p->prof) {
+    bool on;
+    ProfScope(dmwf_plan* p_, hipStream_t s_, int c_)
+        : p(p_), s(s_), cls(c_), on(p_->prof == 1 || (p_->prof == 2 && c_ == PROF_LEG_ANA)) {
+        if (on) {
             a = pool_event(p);
             b = pool_event(p);
             (void)hipEventRecord(a, s);
         }
     }
     ~ProfScope() {
-        if (p->prof) {
+        if (on) {
             (void)hipEventRecord(b, s);
             p->events.push_back({cls, a, b});
         }

@@ -241,8 +241,12 @@ class Plan:
         vals = [float(v) for v in out]
         return vals[0] if self.nmaps == 1 else vals
 
-    def profile(self, enable: bool = True) -> None:
-        _check(load().dmwf_profile_enable(self._h, int(bool(enable))), "dmwf_profile_enable")
+    def profile(self, enable=True) -> None:
+        """True or 1: time every launch; 2: time the Legendre analysis launches
+        only (the solve loop keeps replaying the rest from its graph); False
+        or 0: off."""
+        level = enable if isinstance(enable, int) and not isinstance(enable, bool) else int(bool(enable))
+        _check(load().dmwf_profile_enable(self._h, level), "dmwf_profile_enable")
 
     def profile_read(self) -> dict:
         n = ctypes.c_int()

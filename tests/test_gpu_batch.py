@@ -237,10 +237,11 @@ def test_batched_iteration_cap_stops_every_map():
 
 
 def test_graph_replays_equal_launch_by_launch_iterations():
-    """The solve loop replays one captured iteration as a HIP graph; with
-    kernel timing on it launches every kernel itself.  Both give the same bits,
-    for one map and for a batch, and the graph path gives them again on a
-    second solve (thousands of replays, host synchronisations in between)."""
+    """The solve loop replays one captured iteration as a HIP graph; with every
+    launch timed it launches every kernel itself; with the analysis timed it
+    launches the analysis and replays the rest.  All give the same bits, for
+    one map and for a batch, and the graph path gives them again on a second
+    solve (thousands of replays, host synchronisations in between)."""
     dev = device()
     nside, nmaps = 8, 3
     ps, T, ds = _members(nside, nmaps, first=40)
@@ -254,7 +255,12 @@ def test_graph_replays_equal_launch_by_launch_iterations():
         plan.profile(False)
         a_g, s_g, st_g = plan.solve(*a_in, eps_final=1e-8)
         a_g2, s_g2, _ = plan.solve(*a_in, eps_final=1e-8)
-        for x, y in ((a_e, a_g), (s_e, s_g), (a_g, a_g2), (s_g, s_g2)):
+        plan.profile(2)   # analysis timed between events, the rest replayed
+        a_s, s_s, _ = plan.solve(*a_in, eps_final=1e-8)
+        prof = plan.profile_read()
+        plan.profile(False)
+        assert prof["legendre_analysis"][0] > 0 and prof["legendre_synthesis"][0] == 0
+        for x, y in ((a_e, a_g), (s_e, s_g), (a_g, a_g2), (s_g, s_g2), (a_e, a_s), (s_e, s_s)):
             np.testing.assert_array_equal(x.cpu().numpy(), y.cpu().numpy())
         st_e = st_e if isinstance(st_e, list) else [st_e]
         st_g = st_g if isinstance(st_g, list) else [st_g]
