@@ -668,11 +668,36 @@ const int kClassMaxM[kRingClasses] = {1024, 2048, 4096, 8192};
 
 size_t class_lds(int c) { return (size_t)(kClassMaxM[c] + kClassMaxM[c] / 16) * sizeof(double2); }
 
+// Length n of ring pair q's rings and the FFT length M (n, or the Bluestein
+// length for n not a power of two).
+void ring_lengths(const dmwf_plan* p, int q, int* n_out, int* M_out, bool* blue_out) {
+    const int r = q + 1;
+    const int n = r < p->nside ? 4 * r : 4 * p->nside;
+    const bool b = (n & (n - 1)) != 0;
+    int M = n;
+    if (b) {
+        M = 1;
+        while (M < 2 * n - 1) M <<= 1;
+    }
+    *n_out = n;
+    *M_out = M;
+    *blue_out = b;
+}
+
+// Appends the ring pairs of L to all in XCD-aware order: block b runs on XCD
+// b mod 8, and consecutive blocks of one XCD take consecutive ring pairs.
+void append_xcd_order(const std::vector<int>& L, std::vector<int>& all) {
+    const int nb = (int)L.size();
+    int start[9] = {0};
+    for (int x = 0; x < 8; ++x) start[x + 1] = start[x] + nb / 8 + (x < nb % 8 ? 1 : 0);
+    for (int b = 0; b < nb; ++b) all.push_back(L[start[b % 8] + b / 8]);
+}
+
 }  // namespace
 
 void free_ring_tables(dmwf_plan* p) {
     void* bufs[] = {p->d_ring_M, p->d_ring_blue, p->d_ring_coff, p->d_ring_boff, p->d_chirp,
-                    p->d_bspec,  p->d_ring_class};
+                    p->d_bspec,  p->d_ring_class, p->d_pipe_class};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (int i = 0; i < 3; ++i) {
@@ -680,24 +705,77 @@ void free_ring_tables(dmwf_plan* p) {
         if (p->ring_join[i]) (void)hipEventDestroy(p->ring_join[i]);
     }
     if (p->ring_fork) (void)hipEventDestroy(p->ring_fork);
+    if (p->pipe_stream) (void)hipStreamDestroy(p->pipe_stream);
+    for (int i = 0; i < kMaxPipe; ++i)
+        if (p->pipe_syn[i]) (void)hipEventDestroy(p->pipe_syn[i]);
+    if (p->pipe_join) (void)hipEventDestroy(p->pipe_join);
+}
+
+dmwf_status set_pipe_groups(dmwf_plan* p, int ngroups) {
+    const int nq = p->nq;
+    const int G = std::min(std::max(ngroups, 0), kMaxPipe);
+    const int size = G >= 2 ? ((nq + G - 1) / G + kPipeAlign - 1) / kPipeAlign * kPipeAlign : nq;
+    const int ng = (nq + size - 1) / size;
+    if (G < 2 || ng < 2) {
+        p->npipe = 0;
+        return DMWF_OK;
+    }
+    if (!p->pipe_stream) {
+        DMWF_HIP(hipStreamCreateWithFlags(&p->pipe_stream, hipStreamNonBlocking));
+        for (int i = 0; i < kMaxPipe; ++i)
+            DMWF_HIP(hipEventCreateWithFlags(&p->pipe_syn[i], hipEventDisableTiming));
+        DMWF_HIP(hipEventCreateWithFlags(&p->pipe_join, hipEventDisableTiming));
+    }
+    std::vector<int> all;
+    double cost[kMaxPipe] = {};
+    for (int g = 0; g < ng; ++g) {
+        const int qa = g * size, qb = std::min(nq, qa + size);
+        p->pipe_q[g] = qa;
+        std::vector<int> lists[kRingClasses];
+        for (int q = qa; q < qb; ++q) {
+            int n, M;
+            bool b;
+            ring_lengths(p, q, &n, &M, &b);
+            lists[ring_class(M)].push_back(q);
+            // FFT work of the ring pair: two transforms, twice that for Bluestein
+            cost[g] += (b ? 2.0 : 1.0) * M * std::log2((double)M);
+        }
+        for (int c = 0; c < kRingClasses; ++c) {
+            p->pclass_off[g][c] = (int)all.size();
+            append_xcd_order(lists[c], all);
+        }
+        p->pclass_off[g][kRingClasses] = (int)all.size();
+    }
+    p->pipe_q[ng] = nq;
+    // the group with the most ring work first, the least last: only the last
+    // group's ring stage has no synthesis left to overlap with
+    for (int g = 0; g < ng; ++g) p->pipe_order[g] = g;
+    std::stable_sort(p->pipe_order, p->pipe_order + ng,
+                     [&](int x, int y) { return cost[x] > cost[y]; });
+    int* d = nullptr;
+    if (hipMalloc((void**)&d, all.size() * sizeof(int)) != hipSuccess ||
+        hipMemcpy(d, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+        if (d) (void)hipFree(d);
+        p->npipe = 0;
+        set_error("allocation of the pipeline ring lists failed");
+        return DMWF_ERR_OOM;
+    }
+    if (p->d_pipe_class) (void)hipFree(p->d_pipe_class);
+    p->d_pipe_class = d;
+    p->npipe = ng;
+    return DMWF_OK;
 }
 
 dmwf_status build_ring_tables(dmwf_plan* p) {
     const int nq = p->nq;
     std::vector<int> nph(nq), Mq(nq), blue(nq);
     std::vector<long long> coff(nq, 0), boff(nq, 0);
-    const int N = p->nside;
     long long csum = 0, bsum = 0;
     for (int q = 0; q < nq; ++q) {
-        const int r = q + 1;
-        const int n = r < N ? 4 * r : 4 * N;
+        int n, M;
+        bool b;
+        ring_lengths(p, q, &n, &M, &b);
         nph[q] = n;
-        const bool b = (n & (n - 1)) != 0;
-        int M = n;
-        if (b) {
-            M = 1;
-            while (M < 2 * n - 1) M <<= 1;
-        }
         if (M > 8192) {
             set_error("ring FFT longer than 8192 points (nside > 1024) is not implemented");
             return DMWF_ERR_UNSUPPORTED;
@@ -723,18 +801,13 @@ dmwf_status build_ring_tables(dmwf_plan* p) {
             C[coff[q] + t] = make_double2((double)cosl(ang), (double)sinl(ang));
         }
     }
-    // launch classes in XCD-aware order: block b runs on XCD b mod 8 and
-    // consecutive blocks of one XCD take consecutive ring pairs
+    // launch classes in XCD-aware order
     std::vector<int> lists[kRingClasses];
     for (int q = 0; q < nq; ++q) lists[ring_class(Mq[q])].push_back(q);
     std::vector<int> all;
     for (int c = 0; c < kRingClasses; ++c) {
         p->class_off[c] = (int)all.size();
-        const std::vector<int>& L = lists[c];
-        const int nb = (int)L.size();
-        int start[9] = {0};
-        for (int x = 0; x < 8; ++x) start[x + 1] = start[x] + nb / 8 + (x < nb % 8 ? 1 : 0);
-        for (int b = 0; b < nb; ++b) all.push_back(L[start[b % 8] + b / 8]);
+        append_xcd_order(lists[c], all);
     }
     p->class_off[kRingClasses] = (int)all.size();
     for (int i = 0; i < kRingClasses - 1; ++i) {
@@ -780,7 +853,13 @@ dmwf_status build_ring_tables(dmwf_plan* p) {
 }
 
 dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const RingMaps& rm,
-                        const RingIO& io, hipStream_t s) {
+                        const RingIO& io, hipStream_t s, int grp) {
+    if (grp >= p->npipe) {
+        set_error("ring pipeline group out of range");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    const int* off = grp < 0 ? p->class_off : p->pclass_off[grp];
+    const int* qlists = grp < 0 ? p->d_ring_class : p->d_pipe_class;
     RingArgs a;
     a.g = p->geom();
     a.nq = p->nq;
@@ -815,14 +894,14 @@ dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const RingMa
     ProfScope ps(p, s, cls);
     DMWF_HIP(hipEventRecord(p->ring_fork, s));
     for (int c = kRingClasses - 1; c >= 0; --c) {
-        const int nb = p->class_off[c + 1] - p->class_off[c];
+        const int nb = off[c + 1] - off[c];
         if (nb == 0) continue;
         hipStream_t sc = s;
         if (c < kRingClasses - 1) {
             sc = p->ring_side[c];
             DMWF_HIP(hipStreamWaitEvent(sc, p->ring_fork, 0));
         }
-        a.qlist = p->d_ring_class + p->class_off[c];
+        a.qlist = qlists + off[c];
         launch_class(c, dim3(nb, rm.nm), class_lds(c), sc, a);
         DMWF_HIP(hipGetLastError());
         if (c < kRingClasses - 1) {

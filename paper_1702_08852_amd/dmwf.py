@@ -72,6 +72,9 @@ def load() -> ctypes.CDLL:
                                ctypes.POINTER(_Stats), vp, sz, vp]
     lib.dmwf_autotune.argtypes = [vp, vp, sz, vp, ctypes.POINTER(ci), ctypes.POINTER(ctypes.c_float)]
     lib.dmwf_set_tiles.argtypes = [vp, ci, ci, ci, ci]
+    lib.dmwf_set_pipeline.argtypes = [vp, ci]
+    lib.dmwf_pipeline_groups.argtypes = [vp]
+    lib.dmwf_pipeline_groups.restype = ci
     lib.dmwf_wf_residual.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(cd), vp, sz, vp]
     lib.dmwf_profile_enable.argtypes = [vp, ci]
     lib.dmwf_profile_read.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ctypes.c_char_p),
@@ -230,6 +233,15 @@ class Plan:
     def set_tiles(self, syn_k: int, syn_mb: int, ana_k: int, ana_mb: int = 1) -> None:
         _check(load().dmwf_set_tiles(self._h, int(syn_k), int(syn_mb), int(ana_k), int(ana_mb)),
                "dmwf_set_tiles")
+
+    def set_pipeline(self, groups: int) -> None:
+        """Split the iteration's synthesis and ring stage into this many
+        ring-pair groups that overlap (0 or 1: off)."""
+        _check(load().dmwf_set_pipeline(self._h, int(groups)), "dmwf_set_pipeline")
+
+    @property
+    def pipeline_groups(self) -> int:
+        return int(load().dmwf_pipeline_groups(self._h))
 
     def wf_residual(self, cl, d, ninv, alm):
         """FP64 residual of the Wiener filter system: a float for a one-map
