@@ -359,7 +359,7 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn(SynArgs a) {
         double2* spec = a.spec + (long long)(mg + i) * a.spec_map;
         for (int idx = threadIdx.x; idx < K * 64 * kSlots; idx += 64 * kLegWaves) {
             const int slot = idx % kSlots, rr = idx / kSlots;
-            const int q = tile.chunk * (64 * K) + rr;
+            const int q = (a.c0 + tile.chunk) * (64 * K) + rr;
             const int mm = m0 + (slot >> 1);
             if (q < nq && mm <= ei_)
                 spec[((size_t)q * a.lp + mm) * 2 + (slot & 1)] = stage[rr >> 6][rr & 63][slot >> 1][slot & 1];
