@@ -188,16 +188,13 @@ dmwf_status dmwf_autotune(dmwf_plan* plan, void* dev_ws, size_t ws_bytes, void* 
  * call needs first != 0).  DMWF_ERR_INVALID_ARG for other values. */
 dmwf_status dmwf_set_tiles(dmwf_plan* plan, int syn_k, int syn_mb, int ana_k, int ana_mb);
 
-/* Pipelined iteration (Algorithm 2's synthesis and pixel step, overlapped):
- * the ring pairs split into `groups` groups of whole multiples of 128 ring
- * pairs, the Legendre synthesis launched group by group on the caller's
- * stream and each group's ring stage on a stream of the plan as soon as that
- * group's synthesis has ended.  SWITCHED OFF: its first solve ended the
- * process with a host segmentation fault whose cause was not found.  groups
- * 0 or 1 (no pipeline, the default) return DMWF_OK; 2..8 return
+/* Pipelined iteration (overlap of the synthesis and the ring stage by
+ * ring-pair groups): NOT BUILT.  It was removed after its first solve ended
+ * the process with a host segmentation fault whose cause was not found.
+ * groups 0 or 1 (no pipeline) return DMWF_OK; 2..8 return
  * DMWF_ERR_UNSUPPORTED; other values DMWF_ERR_INVALID_ARG. */
 dmwf_status dmwf_set_pipeline(dmwf_plan* plan, int groups);
-/* Groups in use (0: no pipeline), -1 for a NULL plan. */
+/* Groups in use: always 0 (no pipeline); -1 for a NULL plan. */
 int dmwf_pipeline_groups(const dmwf_plan* plan);
 
 /* ||A x - y|| / ||y|| with A = 1 + C^1/2 Y^H W Y C^1/2, x = C^-1/2 a,

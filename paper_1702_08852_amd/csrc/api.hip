@@ -474,6 +474,7 @@ void dmwf_plan_destroy(dmwf_plan* p) {
         (void)hipEventDestroy(e.start);
         (void)hipEventDestroy(e.stop);
     }
+    for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
     free_ring_tables(p);
     if (p->h_ctrl) (void)hipHostFree(p->h_ctrl);
     for (hipEvent_t e : p->batch_ev)
@@ -805,20 +806,21 @@ dmwf_status dmwf_set_tiles(dmwf_plan* p, int syn_k, int syn_mb, int ana_k, int a
 }
 
 dmwf_status dmwf_set_pipeline(dmwf_plan* p, int groups) {
-    if (!p || groups < 0 || groups > kMaxPipe) {
+    if (!p || groups < 0 || groups > 8) {
         set_error("pipeline groups: 0 to 8");
         return DMWF_ERR_INVALID_ARG;
     }
     if (groups >= 2) {
-        // The first solve with the pipeline on ended the process with a
-        // host segmentation fault, cause not found; the path stays off.
-        set_error("the pipelined iteration is switched off");
+        // Not built: the pipelined iteration was removed after its first
+        // solve ended the process with a host segmentation fault whose cause
+        // was not found.
+        set_error("the pipelined iteration is switched off (not built)");
         return DMWF_ERR_UNSUPPORTED;
     }
-    return set_pipe_groups(p, groups);
+    return DMWF_OK;
 }
 
-int dmwf_pipeline_groups(const dmwf_plan* p) { return p ? p->npipe : -1; }
+int dmwf_pipeline_groups(const dmwf_plan* p) { return p ? 0 : -1; }
 
 // Time every Legendre tile on the plan's own shape (all maps, full band; the
 // instruction stream does not depend on the values) and keep the fastest.
@@ -967,31 +969,10 @@ dmwf_status iterate_rest(dmwf_plan* p, const Ws& W, int k0, int nm, double xi, d
     io.mhi_tab = W.mhi_tab() + (size_t)k0 * kMaxLevels * p->nq;
     io.pix_map = p->npix;
     const RingMaps rm{nm, W.ell(k0), W.ell_ana(k0), 1, W.mhi(k0, p->nq), mhi_ana, 0};
-    if (p->npipe >= 2 && p->prof != 1) {
-        // Pipelined: the synthesis group by group on s; each group's ring
-        // stage on pipe_stream once its synthesis has ended, so that it runs
-        // beside the synthesis of the later groups.  The groups' ring pairs
-        // are disjoint: a group's F rows, pixels and Cauchy partials are
-        // touched by its own launches only.  (Not under per-launch timing,
-        // whose events would time overlapping kernels.)
-        for (int i = 0; i < p->npipe; ++i) {
-            const int g = p->pipe_order[i];
-            st = launch_leg_syn(p, W.ap(k0), W.spec(k0), lm, p->syn_mb, s, p->pipe_q[g],
-                                p->pipe_q[g + 1]);
-            if (st != DMWF_OK) return st;
-            DMWF_HIP(hipEventRecord(p->pipe_syn[i], s));
-            DMWF_HIP(hipStreamWaitEvent(p->pipe_stream, p->pipe_syn[i], 0));
-            st = launch_ring(p, RING_ITER, W.spec(k0), rm, io, p->pipe_stream, g);
-            if (st != DMWF_OK) return st;
-        }
-        DMWF_HIP(hipEventRecord(p->pipe_join, p->pipe_stream));
-        DMWF_HIP(hipStreamWaitEvent(s, p->pipe_join, 0));
-    } else {
-        st = launch_leg_syn(p, W.ap(k0), W.spec(k0), lm, p->syn_mb, s);
-        if (st != DMWF_OK) return st;
-        st = launch_ring(p, RING_ITER, W.spec(k0), rm, io, s);
-        if (st != DMWF_OK) return st;
-    }
+    st = launch_leg_syn(p, W.ap(k0), W.spec(k0), lm, p->syn_mb, s);
+    if (st != DMWF_OK) return st;
+    st = launch_ring(p, RING_ITER, W.spec(k0), rm, io, s);
+    if (st != DMWF_OK) return st;
     {
         ProfScope ps(p, s, PROF_REDUCE);
         if (ctrl)

@@ -106,11 +106,6 @@ struct WsLayout {
 // Blocks of the per-map input screening reduction.
 constexpr int kCheckBlocks = 1024;
 
-// Most ring-pair groups of the pipelined iteration, and their alignment in
-// ring pairs (a whole number of synthesis chunks at either tile).
-constexpr int kMaxPipe = 8;
-constexpr int kPipeAlign = 128;
-
 // The maps of one Legendre launch.
 struct LegMaps {
     int nm;               // maps in the launch
@@ -162,21 +157,6 @@ struct dmwf_plan {
     hipStream_t ring_side[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ring_fork = nullptr;
     hipEvent_t ring_join[3] = {nullptr, nullptr, nullptr};
-    // Pipelined iteration: the ring pairs fall into npipe groups; the
-    // synthesis of each group is a launch of its own on the caller's stream,
-    // and the ring stage of the group follows on pipe_stream as soon as that
-    // launch ends, concurrently with the synthesis of the later groups.
-    // Group g covers ring pairs pipe_q[g] .. pipe_q[g + 1] - 1 and pipe_order
-    // is the launch order.  npipe < 2: the whole synthesis, then the whole
-    // ring stage, on the caller's stream.
-    int npipe = 0;
-    int pipe_q[dmwf::kMaxPipe + 1] = {};
-    int pipe_order[dmwf::kMaxPipe] = {};
-    int* d_pipe_class = nullptr;             // the groups' class lists, concatenated
-    int pclass_off[dmwf::kMaxPipe][5] = {};  // offsets of each group's lists there
-    hipStream_t pipe_stream = nullptr;       // default priority
-    hipEvent_t pipe_syn[dmwf::kMaxPipe] = {};
-    hipEvent_t pipe_join = nullptr;
     dmwf::WsLayout ws;
     // pinned host copy of the control block, read after each batch of the
     // solve loop (two batches in flight)
@@ -265,10 +245,8 @@ __host__ __device__ inline long long alm_base(int m, int lmax) {
 dmwf_status launch_seeds(dmwf_plan* p, hipStream_t s);
 // Legendre stages over the maps of lm.  ap, spec and part point at map 0's
 // slice; the per-map strides are the workspace's.
-// The synthesis covers ring pairs qa .. qb - 1 (qb < 0: to the last), qa on a
-// boundary of its ring chunks (a multiple of 128 always is).
 dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const LegMaps& lm,
-                           int mb, hipStream_t s, int qa = 0, int qb = -1);
+                           int mb, hipStream_t s);
 dmwf_status launch_leg_ana(dmwf_plan* p, const double2* spec, double2* part, const LegMaps& lm,
                            int mb, hipStream_t s);
 
@@ -318,16 +296,11 @@ struct RingMaps {
     const int* mhi_ana;
     int mhi_stride;
 };
-// grp < 0: every ring pair; else the ring pairs of pipeline group grp.
 dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const RingMaps& rm,
-                        const RingIO& io, hipStream_t s, int grp = -1);
+                        const RingIO& io, hipStream_t s);
 // Ring transform tables and launch classes; called by dmwf_plan_create.
 dmwf_status build_ring_tables(dmwf_plan* p);
 void free_ring_tables(dmwf_plan* p);
-// Splits the ring pairs into ngroups pipeline groups (fewer where the ring
-// pairs run out; below two, no pipeline).  Called by dmwf_set_pipeline, which
-// accepts only counts below two: the pipelined path is switched off.
-dmwf_status set_pipe_groups(dmwf_plan* p, int ngroups);
 constexpr int kRingClasses = 4;
 
 }  // namespace dmwf

@@ -172,7 +172,7 @@ struct SynArgs {
     int ell_stride;
     const DevCtrl* ctrl;     // per-map control blocks (solve loop) or NULL
     int lmax, nq, lp, nm;
-    int c0, cn;              // ring chunks c0 .. c0 + cn - 1 of 64 K ring pairs
+    int nchunk;              // ring chunks of 64 K ring pairs
 };
 
 // The analysis takes its coefficient row through LDS, kChunk l at a time per
@@ -273,13 +273,13 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn(SynArgs a) {
     const int w = threadIdx.x >> 6;
     // wave-uniform; readfirstlane lets the compiler use scalar loads for the
     // per-(l, m) coefficients
-    const LegTile tile = leg_tile(a.cn);
+    const LegTile tile = leg_tile(a.nchunk);
     const int m = __builtin_amdgcn_readfirstlane(tile.group * kLegWaves + w);
     if (tile.group * kLegWaves > ell) return;  // whole workgroup above the band limit
     const bool live = m <= ell;
     const int lane = threadIdx.x & 63;
     const int nq = a.nq;
-    const int q0 = (a.c0 + tile.chunk) * (64 * K) + lane;
+    const int q0 = tile.chunk * (64 * K) + lane;
     const size_t mo = (size_t)m * nq;
     double x[K], p1[K], p2[K], s0[K], s1[K];
     double er[MB][K], ei[MB][K], orr[MB][K], oi[MB][K];
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn(SynArgs a) {
         double2* spec = a.spec + (long long)(mg + i) * a.spec_map;
         for (int idx = threadIdx.x; idx < K * 64 * kSlots; idx += 64 * kLegWaves) {
             const int slot = idx % kSlots, rr = idx / kSlots;
-            const int q = (a.c0 + tile.chunk) * (64 * K) + rr;
+            const int q = tile.chunk * (64 * K) + rr;
             const int mm = m0 + (slot >> 1);
             if (q < nq && mm <= ei_)
                 spec[((size_t)q * a.lp + mm) * 2 + (slot & 1)] = stage[rr >> 6][rr & 63][slot >> 1][slot & 1];
@@ -654,20 +654,13 @@ int leg_groups8(const dmwf_plan* p) {
 }  // namespace
 
 dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const LegMaps& lm,
-                           int mb_want, hipStream_t s, int qa, int qb) {
+                           int mb_want, hipStream_t s) {
     const int k = p->syn_k == 1 ? 1 : 2;
-    if (qb < 0) qb = p->nq;
-    // ring pairs qa .. qb - 1; qa on a chunk boundary
-    if (qa < 0 || qa >= qb || qb > p->nq || qa % (64 * k) != 0) {
-        set_error("synthesis ring range not on a chunk boundary");
-        return DMWF_ERR_INVALID_ARG;
-    }
-    const int c0 = qa / (64 * k);
-    const int nchunk = (qb - qa + 64 * k - 1) / (64 * k);
+    const int nchunk = (p->nq + 64 * k - 1) / (64 * k);
     SynArgs a{p->d_x,       p->d_ls,    p->d_s0,        p->d_s1,  p->d_A,
               ap,           p->ws.alm_map, spec,        p->ws.spec_map,
               lm.ell,       lm.ell_stride, lm.ctrl,     p->lmax,  p->nq,
-              p->lp,        lm.nm,      c0,             nchunk};
+              p->lp,        lm.nm,      nchunk};
     ProfScope ps(p, s, PROF_LEG_SYN);
     const int mb = pick_mb(mb_want, lm.nm, 8);
     const dim3 grid(nchunk * leg_groups8(p), (lm.nm + mb - 1) / mb);

@@ -697,7 +697,7 @@ void append_xcd_order(const std::vector<int>& L, std::vector<int>& all) {
 
 void free_ring_tables(dmwf_plan* p) {
     void* bufs[] = {p->d_ring_M, p->d_ring_blue, p->d_ring_coff, p->d_ring_boff, p->d_chirp,
-                    p->d_bspec,  p->d_ring_class, p->d_pipe_class};
+                    p->d_bspec,  p->d_ring_class};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (int i = 0; i < 3; ++i) {
@@ -705,65 +705,6 @@ void free_ring_tables(dmwf_plan* p) {
         if (p->ring_join[i]) (void)hipEventDestroy(p->ring_join[i]);
     }
     if (p->ring_fork) (void)hipEventDestroy(p->ring_fork);
-    if (p->pipe_stream) (void)hipStreamDestroy(p->pipe_stream);
-    for (int i = 0; i < kMaxPipe; ++i)
-        if (p->pipe_syn[i]) (void)hipEventDestroy(p->pipe_syn[i]);
-    if (p->pipe_join) (void)hipEventDestroy(p->pipe_join);
-}
-
-dmwf_status set_pipe_groups(dmwf_plan* p, int ngroups) {
-    const int nq = p->nq;
-    const int G = std::min(std::max(ngroups, 0), kMaxPipe);
-    const int size = G >= 2 ? ((nq + G - 1) / G + kPipeAlign - 1) / kPipeAlign * kPipeAlign : nq;
-    const int ng = (nq + size - 1) / size;
-    if (G < 2 || ng < 2) {
-        p->npipe = 0;
-        return DMWF_OK;
-    }
-    if (!p->pipe_stream) {
-        DMWF_HIP(hipStreamCreateWithFlags(&p->pipe_stream, hipStreamNonBlocking));
-        for (int i = 0; i < kMaxPipe; ++i)
-            DMWF_HIP(hipEventCreateWithFlags(&p->pipe_syn[i], hipEventDisableTiming));
-        DMWF_HIP(hipEventCreateWithFlags(&p->pipe_join, hipEventDisableTiming));
-    }
-    std::vector<int> all;
-    double cost[kMaxPipe] = {};
-    for (int g = 0; g < ng; ++g) {
-        const int qa = g * size, qb = std::min(nq, qa + size);
-        p->pipe_q[g] = qa;
-        std::vector<int> lists[kRingClasses];
-        for (int q = qa; q < qb; ++q) {
-            int n, M;
-            bool b;
-            ring_lengths(p, q, &n, &M, &b);
-            lists[ring_class(M)].push_back(q);
-            // FFT work of the ring pair: two transforms, twice that for Bluestein
-            cost[g] += (b ? 2.0 : 1.0) * M * std::log2((double)M);
-        }
-        for (int c = 0; c < kRingClasses; ++c) {
-            p->pclass_off[g][c] = (int)all.size();
-            append_xcd_order(lists[c], all);
-        }
-        p->pclass_off[g][kRingClasses] = (int)all.size();
-    }
-    p->pipe_q[ng] = nq;
-    // the group with the most ring work first, the least last: only the last
-    // group's ring stage has no synthesis left to overlap with
-    for (int g = 0; g < ng; ++g) p->pipe_order[g] = g;
-    std::stable_sort(p->pipe_order, p->pipe_order + ng,
-                     [&](int x, int y) { return cost[x] > cost[y]; });
-    int* d = nullptr;
-    if (hipMalloc((void**)&d, all.size() * sizeof(int)) != hipSuccess ||
-        hipMemcpy(d, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
-        if (d) (void)hipFree(d);
-        p->npipe = 0;
-        set_error("allocation of the pipeline ring lists failed");
-        return DMWF_ERR_OOM;
-    }
-    if (p->d_pipe_class) (void)hipFree(p->d_pipe_class);
-    p->d_pipe_class = d;
-    p->npipe = ng;
-    return DMWF_OK;
 }
 
 dmwf_status build_ring_tables(dmwf_plan* p) {
@@ -853,13 +794,9 @@ dmwf_status build_ring_tables(dmwf_plan* p) {
 }
 
 dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const RingMaps& rm,
-                        const RingIO& io, hipStream_t s, int grp) {
-    if (grp >= p->npipe) {
-        set_error("ring pipeline group out of range");
-        return DMWF_ERR_INVALID_ARG;
-    }
-    const int* off = grp < 0 ? p->class_off : p->pclass_off[grp];
-    const int* qlists = grp < 0 ? p->d_ring_class : p->d_pipe_class;
+                        const RingIO& io, hipStream_t s) {
+    const int* off = p->class_off;
+    const int* qlists = p->d_ring_class;
     RingArgs a;
     a.g = p->geom();
     a.nq = p->nq;

@@ -184,3 +184,67 @@ def test_batched_nside512_group_sampled():
         assert sts[k].n_iter == 1 and ref.n_iter == 1
         assert rel(alm[k], ref.alm) < 1e-11
         assert rel(smap[k], ref.map) < 1e-11
+
+
+def _solve_and_replay(nside, name, mu0, replay_gpu, replay_oracle, cap, ring_list):
+    """dmwf_solve through the C ABI with replayed per-level counts and an
+    iteration cap, against the oracle replaying the same counts; returns the
+    GPU stats and the oracle result after comparing a and s."""
+    dev = device()
+    p, T, d, w = _problem(name, nside)
+    plan = _plan(nside, p.lmax)
+    alm, smap, st = plan.solve(to_dev(p.cl, dev), to_dev(d, dev), to_dev(w, dev), mu0=mu0,
+                               eps_final=1e-6, eps_coarse=1e-4, replay=replay_gpu, max_iter=cap)
+    alm, smap = alm.cpu().numpy(), smap.cpu().numpy()
+    ref = dm.solve(T, d, w, p.cl, mu0=mu0, eps_final=1e-6, eps_coarse=1e-4, replay=replay_oracle,
+                   max_iter=cap)
+    assert st.n_iter == ref.n_iter == cap
+    nl = len(st.iters_per_level)
+    assert st.iters_per_level == list(ref.iters_per_level)
+    assert st.lmax_per_level == ref.ell_iters[:nl]
+    np.testing.assert_allclose(st.xi_per_level, ref.xis[:nl], rtol=1e-15)
+    assert rel(alm, ref.alm) < 1e-10
+    assert rel(smap, ref.map) < 1e-10
+    z, st_, nph, p0, start = oracle.rings(nside)
+    for r in ring_list:  # every sampled ring on its own
+        sl = slice(start[r - 1], start[r - 1] + nph[r - 1])
+        assert rel(smap[sl], ref.map[sl]) < 1e-10, r
+    return st, ref, p
+
+
+def test_solve_nside1024_cfg3_across_level_switches():
+    """Configuration 3 at full size (Nside 1024, lmax 2048) through dmwf_solve:
+    level 0 starts mid-band (mu0 = C_500, l_iter near 500), one iteration on
+    each of levels 0 and 1 and two on level 2, stopped by the iteration cap.
+    This runs the device level control across two level switches (k_control,
+    the per-level m bounds of every ring pair, the unfold of G to the next
+    level's l_iter) with every ring-length class, and ends on iterations whose
+    previous s is not zero."""
+    from paper_1702_08852_amd import dmwf as b
+    nside = 1024
+    p0 = inp.make_problem("cfg3", nside=nside)
+    mu0 = float(p0.cl[500])
+    nlev = len(dm.level_schedule(dm.alpha_of(p0.ninv), 12 * nside * nside / (4 * math.pi),
+                                 p0.cl, 0.75, mu0))
+    st, ref, p = _solve_and_replay(nside, "cfg3", mu0, [1, 1, 5] + [1] * (nlev - 3),
+                                   [1, 1, 1000] + [1] * (nlev - 3), 4, RINGS_1024)
+    assert st.status == b.ERR_NOT_CONVERGED
+    assert st.iters_per_level == [1, 1, 2]
+    ells = st.lmax_per_level
+    assert 400 <= ells[0] < ells[1] < ells[2] < p.lmax  # the band grows with every switch
+
+
+def test_solve_nside256_cfg2_every_level_replayed():
+    """Configuration 2 (Nside 256, lmax 512) through dmwf_solve over its whole
+    cooling schedule (every level, two iterations each, three on the last):
+    the device level control at every switch up to xi = alpha against the
+    oracle replaying the same counts."""
+    nside = 256
+    p0 = inp.make_problem("cfg2", nside=nside)
+    nlev = len(dm.level_schedule(dm.alpha_of(p0.ninv), 12 * nside * nside / (4 * math.pi),
+                                 p0.cl, 0.75))
+    rep = [2] * (nlev - 1) + [3]
+    st, ref, p = _solve_and_replay(nside, "cfg2", -1.0, rep, rep, sum(rep),
+                                   [1, 2, 100, 255, 256, 257, 511, 512, 513, 700, 1022, 1023])
+    assert st.status == 0 and len(st.iters_per_level) == nlev >= 5
+    assert st.lmax_per_level[-1] == p.lmax

@@ -315,3 +315,66 @@ def test_literal_harmonic_step_is_biased_on_healpix(monkeypatch):
     bad = dm.solve(T, d, w, p.cl, eps_final=1e-10, eps_coarse=1e-4)
     assert rel(good.alm, ref) < 1e-6
     assert rel(bad.alm, ref) > 1e-3
+
+
+# --------------------------------------------------------------------------
+# the warm-start branch and the reported residual, pinned independently
+# --------------------------------------------------------------------------
+def test_warm_start_branch_stays_at_and_converges_to_dense_wf():
+    """The solve started at xi = alpha from a given a_lm (Algorithm 2's loop
+    entered at its last level).  Started at the dense Wiener filter it stays
+    there: the WF is the fixed point of the residual-form step at mu = 0, so the
+    first iterate equals the start and the first Cauchy ratio is at rounding
+    level.  Started 20% away (in every active mode) it converges to the dense
+    solution."""
+    p, T, d, w = sphere_problem(nside=8)
+    ref = dense.wiener_dense(8, p.lmax, p.cl, w, d)
+    stay = dm.solve(T, d, w, p.cl, start_final=True, alm0=ref, replay=[1])
+    assert stay.n_iter == 1
+    assert rel(stay.alm, ref) < 1e-12
+    assert stay.ratios[0] < 1e-12
+    rng = np.random.default_rng(8)
+    act = p.cl[oracle.ell_of_index(p.lmax)] > 0
+    start = ref + 0.2 * np.abs(ref).mean() * rng.standard_normal(ref.shape) * act[:, None]
+    start[:p.lmax + 1, 1] = 0.0
+    assert rel(start, ref) > 0.1
+    res = dm.solve(T, d, w, p.cl, start_final=True, alm0=start, eps_final=1e-13,
+                   max_iter=200000)
+    assert res.converged and len(res.iters_per_level) == 1
+    assert rel(res.alm, ref) < 1e-8
+    assert rel(res.map, T.synth(ref)) < 1e-8
+
+
+def test_wf_residual_matches_independent_scipy_basis():
+    """||A x - y|| / ||y|| (A = 1 + C^1/2 Y^H W Y C^1/2, x = C^-1/2 a,
+    y = C^1/2 Y^H W d) of a perturbed a_lm, built here from scipy's Y_lm with
+    explicit sums over pixels and modes, norms counting m > 0 twice; the
+    oracle's value must agree."""
+    nside, lmax = 4, 8
+    p, T, d, w = sphere_problem(nside=nside, lmax=lmax)
+    rng = np.random.default_rng(4)
+    a = dense.wiener_dense(nside, lmax, p.cl, w, d)
+    a = a + 0.3 * np.abs(a).mean() * rng.standard_normal(a.shape)
+    a[:lmax + 1, 1] = 0.0
+    th, ph = oracle.pixel_angles(nside)
+    Y, s = {}, np.zeros(th.size)
+    for m in range(lmax + 1):
+        for l in range(m, lmax + 1):
+            k = oracle.alm_index(l, m, lmax)
+            Y[k] = (l, m, sph_harm_y(l, m, th, ph))
+            c = a[k, 0] + 1j * a[k, 1]
+            s += (c * Y[k][2]).real * (1.0 if m == 0 else 2.0)
+    r2 = y2 = 0.0
+    for k, (l, m, Ylm) in Y.items():
+        if p.cl[l] <= 0.0:
+            continue
+        sq = math.sqrt(p.cl[l])
+        g = np.sum(w * (d - s) * np.conj(Ylm))
+        yv = sq * np.sum(w * d * np.conj(Ylm))
+        res = (a[k, 0] + 1j * a[k, 1]) / sq - sq * g
+        wt = 1.0 if m == 0 else 2.0
+        r2 += wt * abs(res) ** 2
+        y2 += wt * abs(yv) ** 2
+    want = math.sqrt(r2 / y2)
+    assert want > 1e-3  # a perturbed point, far from the zero at the solution
+    assert dm.wf_residual(T, a, d, w, p.cl) == pytest.approx(want, rel=1e-10)
