@@ -117,6 +117,23 @@ dmwf_status dmwf_workspace_bytes(const dmwf_plan* plan, size_t* bytes);
 dmwf_status dmwf_alm2map(dmwf_plan* plan, const double* dev_alm, double* dev_map,
                          void* dev_ws, size_t ws_bytes, void* stream);
 
+/* Synthesis without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same result as dmwf_alm2map, bit for bit, computed
+ * by the same kernels, with their scratch (the g-scaled a_lm and the ring
+ * Fourier rows of every map) in a fixed 64 MiB device array of the library
+ * instead of a caller's workspace.  Each GPU the library runs on holds that
+ * array until the process ends; its address is looked up when a plan is
+ * created on the device.  The call allocates nothing (no hipMalloc, hipFree
+ * or event creation; kernel timing does not apply to it) and needs nothing
+ * zeroed.  Plans whose scratch exceeds 64 MiB (16 B x nmaps x (n_alm + 64 +
+ * 4 nside lp) with lp = 4 ceil((lmax+1)/4), plus alignment: one map up to
+ * Nside 512 / lmax 1024) get DMWF_ERR_WORKSPACE.  All calls on one GPU share the
+ * array and it keeps the last call's contents: calls that overlap on one GPU
+ * (from several streams or threads) race and give wrong maps. */
+dmwf_status dmwf_alm2map_static(dmwf_plan* plan, const double* dev_alm, double* dev_map,
+                                void* stream);
+
 /* Adjoint: alm_lm = sum_p map_p conj(Y_lm(p)), times Omega = 4 pi / Npix if
  * scale_by_pixel_area != 0 (then it is the method's forward transform F). */
 dmwf_status dmwf_adjoint(dmwf_plan* plan, const double* dev_map, double* dev_alm,

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -445,6 +446,51 @@ RingMaps ring_full(const dmwf_plan* p, const Ws& W, int nm) {
     return RingMaps{nm, W.ell_full(), W.ell_full(), 0, p->d_mhi_full, p->d_mhi_full, 0};
 }
 
+// Fixed device scratch of dmwf_alm2map_static: a file-scope array that every
+// GPU the library runs on holds until the process ends.  Host code never
+// passes its name to a kernel (in host code the name is a host-side stand-in);
+// it uses the device address that hipGetSymbolAddress returns for the device,
+// looked up once per device when a plan is created there.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+__device__ __align__(256) char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Called by dmwf_plan_create with the plan's device current.
+dmwf_status static_scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) {
+        set_error("device index beyond the library's table of scratch addresses");
+        return DMWF_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return DMWF_OK;
+    void* ptr = nullptr;
+    DMWF_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) {
+        set_error("hipGetSymbolAddress returned NULL for the static scratch");
+        return DMWF_ERR_HIP;
+    }
+    g_scratch_ptr[device] = ptr;
+    return DMWF_OK;
+}
+
+void* static_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+// Bytes of the static scratch dmwf_alm2map_static needs for a plan: the band
+// limit int, the g-scaled a_lm and the F rows of every map, in the
+// workspace's per-map strides.
+size_t static_alm2map_bytes(const dmwf_plan* p) {
+    const size_t nm = (size_t)p->nmaps;
+    return 256 + align256(nm * p->ws.alm_map * sizeof(double2)) +
+           nm * p->ws.spec_map * sizeof(double2);
+}
+
 }  // namespace
 }  // namespace dmwf
 
@@ -680,6 +726,9 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
     // analysis (whose lane reduction and registers grow with the maps) across two
     p->syn_mb = p->nmaps >= 4 ? 4 : (p->nmaps >= 2 ? 2 : 1);
     p->ana_mb = p->nmaps >= 2 ? 2 : 1;
+    // device address of the static scratch of dmwf_alm2map_static on this device
+    s = static_scratch_setup(p->device);
+    if (s != DMWF_OK) return fail(s);
     *out = p;
     return DMWF_OK;
 }
@@ -753,6 +802,53 @@ dmwf_status dmwf_alm2map(dmwf_plan* p, const double* alm, double* map, void* ws,
     io.map_out = map;
     io.pix_map = p->npix;
     return launch_ring(p, RING_SYN, W.spec(0), ring_full(p, W, nm), io, s);
+}
+
+dmwf_status dmwf_alm2map_static(dmwf_plan* p, const double* alm, double* map, void* stream) {
+    if (!p || !alm || !map) {
+        set_error("NULL argument");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    const size_t need = static_alm2map_bytes(p);
+    if (need > kStaticScratchBytes) {
+        set_error("dmwf_alm2map_static: the plan needs " + std::to_string(need) +
+                  " bytes of scratch, the static scratch holds " +
+                  std::to_string(kStaticScratchBytes) + "; use dmwf_alm2map with a workspace");
+        return DMWF_ERR_WORKSPACE;
+    }
+    char* base = static_cast<char*>(static_scratch(p->device));
+    if (!base) {
+        set_error("static scratch address unknown for the plan's device");
+        return DMWF_ERR_HIP;
+    }
+    int* ell = reinterpret_cast<int*>(base);
+    double2* ap = reinterpret_cast<double2*>(base + 256);
+    double2* spec = reinterpret_cast<double2*>(
+        base + 256 + align256((size_t)p->nmaps * p->ws.alm_map * sizeof(double2)));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nm = p->nmaps;
+    // no timing events here: recording them may create events
+    const int prof = p->prof;
+    p->prof = 0;
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, ell, p->lmax);
+    hipLaunchKernelGGL(k_prep_syn, alm_grid(p->lmax, 256, nm), dim3(256), 0, s,
+                       reinterpret_cast<const double2*>(alm), p->nalm, p->d_g, ap, p->ws.alm_map,
+                       p->lmax);
+    dmwf_status st = DMWF_OK;
+    if (hipGetLastError() != hipSuccess) {
+        set_error("launch failed in dmwf_alm2map_static");
+        st = DMWF_ERR_HIP;
+    }
+    if (st == DMWF_OK) st = launch_leg_syn(p, ap, spec, LegMaps{nm, ell, 0, nullptr}, p->syn_mb, s);
+    if (st == DMWF_OK) {
+        RingIO io{};
+        io.map_out = map;
+        io.pix_map = p->npix;
+        st = launch_ring(p, RING_SYN, spec,
+                         RingMaps{nm, ell, ell, 0, p->d_mhi_full, p->d_mhi_full, 0}, io, s);
+    }
+    p->prof = prof;
+    return st;
 }
 
 dmwf_status dmwf_adjoint(dmwf_plan* p, const double* map, double* alm, int scale_by_pixel_area,

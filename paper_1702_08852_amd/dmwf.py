@@ -66,6 +66,7 @@ def load() -> ctypes.CDLL:
     lib.dmwf_plan_destroy.restype = None
     lib.dmwf_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
     lib.dmwf_alm2map.argtypes = [vp, vp, vp, vp, sz, vp]
+    lib.dmwf_alm2map_static.argtypes = [vp, vp, vp, vp]
     lib.dmwf_adjoint.argtypes = [vp, vp, vp, ci, vp, sz, vp]
     lib.dmwf_dm_iterate.argtypes = [vp, cd, cd, vp, vp, vp, vp, vp, vp, ci, vp, sz, vp]
     lib.dmwf_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(_Schedule), vp, vp,
@@ -170,6 +171,14 @@ class Plan:
         out = self._map(out)
         _check(load().dmwf_alm2map(self._h, _ptr(alm), _ptr(out), self.ws.data_ptr(),
                                    self.ws_bytes, _stream()), "dmwf_alm2map")
+        return out
+
+    def alm2map_static(self, alm: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """dmwf_alm2map_static: the synthesis with the library's fixed device
+        scratch instead of this plan's workspace (allocates nothing)."""
+        out = self._map(out)
+        _check(load().dmwf_alm2map_static(self._h, _ptr(alm), _ptr(out), _stream()),
+               "dmwf_alm2map_static")
         return out
 
     def adjoint(self, mp: torch.Tensor, scale_by_pixel_area: bool = False,
