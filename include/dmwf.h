@@ -58,7 +58,18 @@ typedef enum {
     DMWF_ERR_OOM = 7            /* device allocation for the plan tables failed    */
 } dmwf_status;
 
-typedef enum { DMWF_FP64 = 0 } dmwf_precision;
+/* Precision of the Legendre contractions (the sums over l and over rings of
+ * the transform pair).  The recurrence that generates lambda_lm, its exponent
+ * rescaling near the poles, the ring FFTs, the pixel and harmonic steps, the
+ * Cauchy sums and the residual are FP64 in every form.
+ *   DMWF_FP64         FP64 on the vector ALUs.
+ *   DMWF_FP32_GEMM    lambda_lm and the coefficients rounded to FP32, products
+ *                     on the matrix cores (v_mfma_f32_*_f32) with FP32
+ *                     accumulation.
+ *   DMWF_BF16X3_GEMM  each FP32 operand split into two BF16 parts (hi + lo),
+ *                     the three products hi*hi + hi*lo + lo*hi on the matrix
+ *                     cores with FP32 accumulation. */
+typedef enum { DMWF_FP64 = 0, DMWF_FP32_GEMM = 1, DMWF_BF16X3_GEMM = 2 } dmwf_precision;
 
 typedef struct dmwf_plan dmwf_plan;
 
@@ -66,7 +77,7 @@ typedef struct {
     int nside;     /* power of two, 1 .. 8192                                  */
     int lmax;      /* 0 .. 3 nside - 1                                         */
     int nmaps;     /* 1 .. 65535; the maps of a plan are transformed and solved together */
-    int precision; /* DMWF_FP64                                                */
+    int precision; /* dmwf_precision                                           */
 } dmwf_plan_desc;
 
 /* Cooling schedule and stopping rule of the solve (paper Algorithm 2 and
@@ -86,6 +97,13 @@ typedef struct {
                                 iterations on level k (n_replay = level count)    */
     int n_replay;
     int want_residual;       /* 1: compute stats.wf_residual (two extra transforms) */
+    double eps_reduced;      /* reduced-precision plans: the last level runs the
+                                matrix-core contractions until the Cauchy ratio
+                                falls below this (or stops improving: 64
+                                iterations without a 1% gain), then continues in
+                                FP64 down to eps_final; coarse levels run reduced
+                                throughout, and replayed solves never switch.
+                                <= 0 selects 1e-5 (FP32) or 1e-4 (BF16X3)      */
 } dmwf_schedule;
 
 /* Per-solve statistics (host memory).  The three arrays are optional
@@ -100,6 +118,7 @@ typedef struct {
     int* iters_per_level;
     double* xi_per_level;
     int* lmax_per_level;   /* l_iter: largest l with C_l > mu on that level    */
+    int iters_reduced;     /* iterations whose contractions ran in reduced precision */
 } dmwf_stats;
 
 /* Create a plan: geometry, Legendre recurrence tables and the per-(m, ring)

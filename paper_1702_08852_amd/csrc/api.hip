@@ -243,7 +243,25 @@ __global__ void k_control(const double* __restrict__ cpart_all, int n, CtrlMaps 
         c->done = 1;
         return;
     }
-    const bool advance = c->replay ? c->it_level >= levels[k].replay : ratio < levels[k].eps;
+    bool advance = c->replay ? c->it_level >= levels[k].replay : ratio < levels[k].eps;
+    if (c->reduced) {
+        c->it_reduced += 1;
+        // Reduced-precision contractions run the coarse levels and the last
+        // level down to eps_reduced (or until the ratio stops improving: 64
+        // iterations without a 1% gain); the last level then continues in
+        // FP64 and only an FP64 iteration can end the solve.  Replayed solves
+        // stay reduced throughout.
+        if (k + 1 >= c->nlev && !c->replay) {
+            if (ratio < 0.99 * c->best) {
+                c->best = ratio;
+                c->stall = 0;
+            } else {
+                c->stall += 1;
+            }
+            if (ratio < c->eps_reduced || c->stall >= 64) c->reduced = 0;
+            advance = false;
+        }
+    }
     // the last level met: converged, even on the capped iteration; else the
     // cap stops the map, also on an iteration that would move to the next
     // level (the host enqueues no iteration beyond the cap)
@@ -381,6 +399,30 @@ __global__ void k_resid_norms(const double2* __restrict__ a, const double2* __re
 // ---------------------------------------------------------------------------
 // host helpers
 // ---------------------------------------------------------------------------
+// The Legendre stages in the plan's precision.  Reduced-precision plans run
+// the matrix-core kernels; inside the solve loop (lm.ctrl set) each map runs
+// in the precision its control block names, so both kernels are launched and
+// each takes its own maps.
+dmwf_status leg_syn(dmwf_plan* p, const double2* ap, double2* spec, LegMaps lm, hipStream_t s) {
+    if (p->prec == DMWF_FP64) return launch_leg_syn(p, ap, spec, lm, p->syn_mb, s);
+    if (!lm.ctrl) return launch_leg_syn_mx(p, ap, spec, lm, s);
+    lm.sel = 1;
+    const dmwf_status st = launch_leg_syn(p, ap, spec, lm, p->syn_mb, s);
+    if (st != DMWF_OK) return st;
+    lm.sel = 2;
+    return launch_leg_syn_mx(p, ap, spec, lm, s);
+}
+
+dmwf_status leg_ana(dmwf_plan* p, const double2* spec, double2* part, LegMaps lm, hipStream_t s) {
+    if (p->prec == DMWF_FP64) return launch_leg_ana(p, spec, part, lm, p->ana_mb, s);
+    if (!lm.ctrl) return launch_leg_ana_mx(p, spec, part, lm, s);
+    lm.sel = 1;
+    const dmwf_status st = launch_leg_ana(p, spec, part, lm, p->ana_mb, s);
+    if (st != DMWF_OK) return st;
+    lm.sel = 2;
+    return launch_leg_ana_mx(p, spec, part, lm, s);
+}
+
 struct Ws {
     char* base;
     int nmaps;
@@ -557,9 +599,10 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
         set_error("nmaps must be in [1, 65535] (the maps of a launch are a grid dimension)");
         return DMWF_ERR_INVALID_ARG;
     }
-    if (desc->precision != DMWF_FP64) {
-        set_error("only DMWF_FP64 is implemented");
-        return DMWF_ERR_UNSUPPORTED;
+    if (desc->precision != DMWF_FP64 && desc->precision != DMWF_FP32_GEMM &&
+        desc->precision != DMWF_BF16X3_GEMM) {
+        set_error("precision must be DMWF_FP64, DMWF_FP32_GEMM or DMWF_BF16X3_GEMM");
+        return DMWF_ERR_INVALID_ARG;
     }
     if (N > 1024) {
         set_error("nside > 1024 needs ring FFTs longer than one workgroup's LDS; not implemented");
@@ -569,6 +612,7 @@ dmwf_status dmwf_plan_create(const dmwf_plan_desc* desc, dmwf_plan** out) {
     p->nside = N;
     p->lmax = desc->lmax;
     p->nmaps = desc->nmaps;
+    p->prec = desc->precision;
     p->nq = 2 * N;
     p->nrings = 4 * N - 1;
     p->npix = 12LL * N * N;
@@ -796,7 +840,7 @@ dmwf_status dmwf_alm2map(dmwf_plan* p, const double* alm, double* map, void* ws,
                            p->ws.alm_map, p->lmax);
     }
     DMWF_HIP(hipGetLastError());
-    st = launch_leg_syn(p, W.ap(0), W.spec(0), LegMaps{nm, W.ell_full(), 0, nullptr}, p->syn_mb, s);
+    st = leg_syn(p, W.ap(0), W.spec(0), LegMaps{nm, W.ell_full(), 0, nullptr}, s);
     if (st != DMWF_OK) return st;
     RingIO io{};
     io.map_out = map;
@@ -839,7 +883,7 @@ dmwf_status dmwf_alm2map_static(dmwf_plan* p, const double* alm, double* map, vo
         set_error("launch failed in dmwf_alm2map_static");
         st = DMWF_ERR_HIP;
     }
-    if (st == DMWF_OK) st = launch_leg_syn(p, ap, spec, LegMaps{nm, ell, 0, nullptr}, p->syn_mb, s);
+    if (st == DMWF_OK) st = leg_syn(p, ap, spec, LegMaps{nm, ell, 0, nullptr}, s);
     if (st == DMWF_OK) {
         RingIO io{};
         io.map_out = map;
@@ -871,8 +915,7 @@ dmwf_status dmwf_adjoint(dmwf_plan* p, const double* map, double* alm, int scale
     io.pix_map = p->npix;
     st = launch_ring(p, RING_ANA, W.spec(0), ring_full(p, W, nm), io, s);
     if (st != DMWF_OK) return st;
-    st = launch_leg_ana(p, W.spec(0), W.part(0), LegMaps{nm, W.ell_full(), 0, nullptr}, p->ana_mb,
-                        s);
+    st = leg_ana(p, W.spec(0), W.part(0), LegMaps{nm, W.ell_full(), 0, nullptr}, s);
     if (st != DMWF_OK) return st;
     {
         ProfScope ps(p, s, PROF_DIAG);
@@ -1034,8 +1077,7 @@ namespace {
 // dmwf_dm_iterate sums the Cauchy partials into cauchy_out.
 // The iteration's first launch, the Legendre analysis of the residual spectrum.
 dmwf_status iterate_ana(dmwf_plan* p, const Ws& W, int k0, int nm, DevCtrl* ctrl, hipStream_t s) {
-    return launch_leg_ana(p, W.spec(k0), W.part(k0), LegMaps{nm, W.ell(k0), 1, ctrl}, p->ana_mb,
-                          s);
+    return leg_ana(p, W.spec(k0), W.part(k0), LegMaps{nm, W.ell(k0), 1, ctrl}, s);
 }
 
 // The rest of the iteration after the analysis.
@@ -1065,7 +1107,7 @@ dmwf_status iterate_rest(dmwf_plan* p, const Ws& W, int k0, int nm, double xi, d
     io.mhi_tab = W.mhi_tab() + (size_t)k0 * kMaxLevels * p->nq;
     io.pix_map = p->npix;
     const RingMaps rm{nm, W.ell(k0), W.ell_ana(k0), 1, W.mhi(k0, p->nq), mhi_ana, 0};
-    st = launch_leg_syn(p, W.ap(k0), W.spec(k0), lm, p->syn_mb, s);
+    st = leg_syn(p, W.ap(k0), W.spec(k0), lm, s);
     if (st != DMWF_OK) return st;
     st = launch_ring(p, RING_ITER, W.spec(k0), rm, io, s);
     if (st != DMWF_OK) return st;
@@ -1215,6 +1257,10 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
         set_error("schedule: need 0 < beta < 1, eps > 0, max_iter >= 1");
         return DMWF_ERR_INVALID_ARG;
     }
+    // the reduced contractions hand the last level over to FP64 below this ratio
+    const double eps_red = sc->eps_reduced > 0.0
+                               ? sc->eps_reduced
+                               : (p->prec == DMWF_BF16X3_GEMM ? 1e-4 : 1e-5);
     const int nm = p->nmaps;
     if (stats)
         for (int k = 0; k < nm; ++k)
@@ -1315,6 +1361,9 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
         c.max_iter = sc->max_iter;
         c.replay = sc->replay_iters ? 1 : 0;
         c.alpha = alpha[k];
+        c.reduced = p->prec != DMWF_FP64 ? 1 : 0;
+        c.eps_reduced = eps_red;
+        c.best = INFINITY;
         c0[k] = c;
         nl_max = std::max(nl_max, c.nlev);
         DMWF_HIP(hipMemcpyAsync(W.levels(k), lv[k].data(), lv[k].size() * sizeof(DevLevel),
@@ -1340,8 +1389,7 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
             hipLaunchKernelGGL(k_prep_syn, alm_grid(L, 256, nm), dim3(256), 0, s, a, p->nalm,
                                p->d_g, W.ap(0), p->ws.alm_map, L);
         }
-        st = launch_leg_syn(p, W.ap(0), W.spec(0), LegMaps{nm, W.ell_full(), 0, nullptr},
-                            p->syn_mb, s);
+        st = leg_syn(p, W.ap(0), W.spec(0), LegMaps{nm, W.ell_full(), 0, nullptr}, s);
         if (st != DMWF_OK) return st;
         RingIO io{};
         io.map_out = map_all;
@@ -1503,6 +1551,7 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
             }
             S.n_levels = nlev;
             S.n_iter = fin[k].total;
+            S.iters_reduced = fin[k].it_reduced;
             S.alpha = alpha[k];
             S.final_cauchy = fin[k].ratio;
             S.wf_residual = -1.0;

@@ -75,7 +75,13 @@ struct DevCtrl {
     int level, it_level, total, nlev, max_iter, replay;
     double xi, mu, xi_over_sigma, ratio;
     double alpha;  // min N over unmasked pixels of this map
-    double pad;
+    int reduced;      // reduced-precision plan: 1 while the Legendre contractions
+                      // of this map run on the matrix cores, 0 once they run in FP64
+    int it_reduced;   // iterations run with the reduced contractions
+    double eps_reduced;  // on the last level, below this ratio the map switches to FP64
+    double best;      // smallest ratio seen on the last level in reduced precision
+    int stall;        // iterations since `best` last improved by 1%
+    int pad;
 };
 // Most cooling levels one solve may have (the per-level m-bound table is
 // kMaxLevels x ring pairs ints of workspace).
@@ -112,12 +118,17 @@ struct LegMaps {
     const int* ell;       // band limit of map k at ell[k * ell_stride] (device)
     int ell_stride;       // 0: one band limit for every map
     const DevCtrl* ctrl;  // per-map control blocks, or NULL; a stopped map is skipped
+    int sel = 0;          // with ctrl: 0 every map, 1 the maps whose contraction runs
+                          // in FP64, 2 those on the matrix cores (DevCtrl::reduced)
 };
 
 }  // namespace dmwf
 
 struct dmwf_plan {
     int nside, lmax, nmaps, nq, nrings, device;
+    // Legendre contraction: DMWF_FP64 (VALU), DMWF_FP32_GEMM or DMWF_BF16X3_GEMM
+    // (matrix cores; the recurrence stays FP64)
+    int prec = DMWF_FP64;
     long long npix, nalm;
     int nchunk_ana;  // analysis ring chunks (partial-sum rows per map)
     // Legendre tiles, set by default and by dmwf_autotune.  Synthesis: ring
@@ -249,6 +260,13 @@ dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const
                            int mb, hipStream_t s);
 dmwf_status launch_leg_ana(dmwf_plan* p, const double2* spec, double2* part, const LegMaps& lm,
                            int mb, hipStream_t s);
+// The same two stages with the contraction on the matrix cores in the plan's
+// reduced precision (legendre_mx.hip); every map of lm, or with lm.ctrl the
+// maps lm.sel selects.
+dmwf_status launch_leg_syn_mx(dmwf_plan* p, const double2* ap, double2* spec, const LegMaps& lm,
+                              hipStream_t s);
+dmwf_status launch_leg_ana_mx(dmwf_plan* p, const double2* spec, double2* part, const LegMaps& lm,
+                              hipStream_t s);
 
 // Ring stage modes.  SYN: F -> map.  ANA*: a pixel map -> G, the map being
 // map_in (ANA), d on unmasked pixels (ANA_FIRST), w (d - map_in) (ANA_RESID),

@@ -27,22 +27,12 @@
 // through LDS once per block of 16 l.  K and MB are per-plan tiles.
 #include <climits>
 
-#include "common.h"
+#include "legendre_dev.h"
 
 namespace dmwf {
 namespace {
 
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-    return v;
-}
 
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
-}
 
 // lambda_mm(x_q) for m = 0..lmax as mant * 2^expo: lambda_00 = 1/sqrt(4 pi),
 // lambda_mm = -sqrt((2m+1)/(2m)) sin(theta) lambda_{m-1,m-1}.  The mantissa is
@@ -143,37 +133,10 @@ __global__ void k_mhi(int lmax, int nq, const int* __restrict__ lsmin, int ell,
     mhi[q] = m_bound(lsmin + (size_t)q * (lmax + 1), ell, lmax);
 }
 
-// Workgroup b of a 1-D grid runs on XCD b mod 8 (round-robin dispatch).  Give
-// each XCD whole m-groups, all ring chunks of a group together, so that the
-// group's coefficient rows are fetched into a single L2; groups in order of
-// decreasing work (increasing m) within every XCD.
-struct LegTile {
-    int chunk, group;
-};
-__device__ __forceinline__ LegTile leg_tile(int nchunk) {
-    const int b = blockIdx.x, xcd = b & 7, slot = b >> 3;
-    return {slot % nchunk, (slot / nchunk) * 8 + xcd};
-}
 
 // ---------------------------------------------------------------------------
 // synthesis
 // ---------------------------------------------------------------------------
-struct SynArgs {
-    const double* x;
-    const int* ls;
-    const double* s0;
-    const double* s1;
-    const double* A;
-    const double2* ap;       // pre-scaled a_lm of map 0; map k at ap + k * ap_map
-    long long ap_map;
-    double2* spec;           // F rows of map 0; map k at spec + k * spec_map
-    long long spec_map;
-    const int* ell;          // band limit of map k at ell[k * ell_stride]
-    int ell_stride;
-    const DevCtrl* ctrl;     // per-map control blocks (solve loop) or NULL
-    int lmax, nq, lp, nm;
-    int nchunk;              // ring chunks of 64 K ring pairs
-};
 
 // The analysis takes its coefficient row through LDS, kChunk l at a time per
 // wave: each lane fetches one l of the next chunk with a vector load while
@@ -187,12 +150,6 @@ constexpr int kChunk = 64;
 
 
 
-// Orders this wave's LDS writes before its later LDS reads (and reads before
-// later writes); the other waves of the workgroup use their own LDS region.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
 
 // One even/odd pair of recurrence steps (l even offset from m, l+1 odd) for
 // the K rings of a lane, contracted with the coefficients of MB maps: the
@@ -230,35 +187,7 @@ __device__ __forceinline__ void syn_pair(int l, bool odd_live, const double* __r
     }
 }
 
-// Rings whose recurrence starts at block l take their seed pair; the others
-// either run already or still hold (0, 0) and contribute nothing.
-template <int K>
-__device__ __forceinline__ void inject(int l, const int (&ls)[K], const double (&s0)[K],
-                                       const double (&s1)[K], double (&p1)[K], double (&p2)[K]) {
-#pragma unroll
-    for (int t = 0; t < K; ++t)
-        if (ls[t] == l) {
-            p2[t] = s0[t];
-            p1[t] = s1[t];
-        }
-}
 
-// Band limits of the MB maps of this workgroup's map group: -1 for a map past
-// the end of the batch or whose solve has stopped.  Returns their maximum.
-template <int MB>
-__device__ __forceinline__ int group_ells(int mg, int nm, const int* ell, int ell_stride,
-                                          const DevCtrl* ctrl, int (&ellm)[MB]) {
-    int e = -1;
-#pragma unroll
-    for (int i = 0; i < MB; ++i) {
-        const int k = mg + i;
-        int v = -1;
-        if (k < nm && !(ctrl && ctrl[k].done)) v = ell[k * ell_stride];
-        ellm[i] = v;
-        e = max(e, v);
-    }
-    return e;
-}
 
 template <int K, int MB>
 __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn(SynArgs a) {
@@ -268,7 +197,7 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn(SynArgs a) {
     __shared__ double2 stage[K][64][kLegWaves][2];
     const int mg = blockIdx.y * MB;
     int ellm[MB];
-    const int ell = group_ells<MB>(mg, a.nm, a.ell, a.ell_stride, a.ctrl, ellm);
+    const int ell = group_ells<MB>(mg, a.nm, a.ell, a.ell_stride, a.ctrl, a.sel, ellm);
     if (ell < 0) return;
     const int w = threadIdx.x >> 6;
     // wave-uniform; readfirstlane lets the compiler use scalar loads for the
@@ -370,22 +299,6 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn(SynArgs a) {
 // ---------------------------------------------------------------------------
 // analysis
 // ---------------------------------------------------------------------------
-struct AnaArgs {
-    const double* x;
-    const int* ls;
-    const double* s0;
-    const double* s1;
-    const double* A;
-    const double2* spec;     // G rows of map 0; map k at spec + k * spec_map
-    long long spec_map;
-    double2* part;           // partial sums of map 0, chunk c at part + c * part_stride;
-    size_t part_stride;      // map k at part + k * part_map
-    long long part_map;
-    const int* ell;          // band limit of map k at ell[k * ell_stride]
-    int ell_stride;
-    const DevCtrl* ctrl;     // per-map control blocks (solve loop) or NULL
-    int lmax, nq, lp, nm;
-};
 
 // Cross-lane sums through the lane-swap instructions (no LDS).  xsum32(a, b):
 // lanes 0..31 return a_i + a_{i+32}, lanes 32..63 return b_{i-32} + b_i.
@@ -479,7 +392,7 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
     __shared__ double coef[kLegWaves][2][kChunk];  // per wave: two chunks of A
     const int mg = blockIdx.y * MB;
     int ellm[MB];
-    const int ell = group_ells<MB>(mg, a.nm, a.ell, a.ell_stride, a.ctrl, ellm);
+    const int ell = group_ells<MB>(mg, a.nm, a.ell, a.ell_stride, a.ctrl, a.sel, ellm);
     const int w = threadIdx.x >> 6;
     const LegTile tile = leg_tile((a.nq + 64 * K - 1) / (64 * K));
     const int m = __builtin_amdgcn_readfirstlane(tile.group * kLegWaves + w);
@@ -637,9 +550,6 @@ dmwf_status launch_seeds(dmwf_plan* p, hipStream_t s) {
     return DMWF_OK;
 }
 
-namespace {
-
-// Largest instantiated maps-per-wave count <= want and <= nm.
 int pick_mb(int want, int nm, int cap) {
     int mb = 1;
     while (mb * 2 <= want && mb * 2 <= nm && mb * 2 <= cap) mb *= 2;
@@ -651,16 +561,14 @@ int leg_groups8(const dmwf_plan* p) {
     return ((p->lmax + kLegWaves) / kLegWaves + 7) / 8 * 8;
 }
 
-}  // namespace
-
 dmwf_status launch_leg_syn(dmwf_plan* p, const double2* ap, double2* spec, const LegMaps& lm,
                            int mb_want, hipStream_t s) {
     const int k = p->syn_k == 1 ? 1 : 2;
     const int nchunk = (p->nq + 64 * k - 1) / (64 * k);
     SynArgs a{p->d_x,       p->d_ls,    p->d_s0,        p->d_s1,  p->d_A,
               ap,           p->ws.alm_map, spec,        p->ws.spec_map,
-              lm.ell,       lm.ell_stride, lm.ctrl,     p->lmax,  p->nq,
-              p->lp,        lm.nm,      nchunk};
+              lm.ell,       lm.ell_stride, lm.ctrl,     lm.sel,   p->lmax,
+              p->nq,        p->lp,      lm.nm,          nchunk};
     ProfScope ps(p, s, PROF_LEG_SYN);
     const int mb = pick_mb(mb_want, lm.nm, 8);
     const dim3 grid(nchunk * leg_groups8(p), (lm.nm + mb - 1) / mb);
@@ -690,8 +598,8 @@ dmwf_status launch_leg_ana(dmwf_plan* p, const double2* spec, double2* part, con
                            int mb_want, hipStream_t s) {
     AnaArgs a{p->d_x,   p->d_ls,        p->d_s0,  p->d_s1, p->d_A,
               spec,     p->ws.spec_map, part,     (size_t)p->nalm + kTablePad,
-              p->ws.part_map, lm.ell,   lm.ell_stride, lm.ctrl, p->lmax,
-              p->nq,    p->lp,          lm.nm};
+              p->ws.part_map, lm.ell,   lm.ell_stride, lm.ctrl, lm.sel,
+              p->lmax,  p->nq,          p->lp,    lm.nm};
     ProfScope ps(p, s, PROF_LEG_ANA);
     const int mb = pick_mb(mb_want, lm.nm, 2);
     const dim3 grid(p->nchunk_ana * leg_groups8(p), (lm.nm + mb - 1) / mb);

@@ -15,6 +15,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmwf.so")
 
+FP64, FP32_GEMM, BF16X3_GEMM = 0, 1, 2  # dmwf_precision: form of the Legendre contractions
+
 STATUS = {0: "ok", 1: "invalid argument", 2: "workspace", 3: "HIP error", 4: "not converged",
           5: "non-finite", 6: "unsupported", 7: "out of memory"}
 OK, ERR_INVALID_ARG, ERR_WORKSPACE, ERR_HIP, ERR_NOT_CONVERGED, ERR_NONFINITE, ERR_UNSUPPORTED, \
@@ -37,7 +39,7 @@ class _Schedule(ctypes.Structure):
                 ("eps_final", ctypes.c_double), ("eps_coarse", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("start_final", ctypes.c_int),
                 ("replay_iters", ctypes.POINTER(ctypes.c_int)), ("n_replay", ctypes.c_int),
-                ("want_residual", ctypes.c_int)]
+                ("want_residual", ctypes.c_int), ("eps_reduced", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -45,7 +47,7 @@ class _Stats(ctypes.Structure):
                 ("final_cauchy", ctypes.c_double), ("wf_residual", ctypes.c_double),
                 ("cap_levels", ctypes.c_int), ("iters_per_level", ctypes.POINTER(ctypes.c_int)),
                 ("xi_per_level", ctypes.POINTER(ctypes.c_double)),
-                ("lmax_per_level", ctypes.POINTER(ctypes.c_int))]
+                ("lmax_per_level", ctypes.POINTER(ctypes.c_int)), ("iters_reduced", ctypes.c_int)]
 
 
 _lib = None
@@ -120,20 +122,22 @@ class SolveStats:
     xi_per_level: list = field(default_factory=list)
     lmax_per_level: list = field(default_factory=list)
     status: int = OK
+    iters_reduced: int = 0
 
 
 class Plan:
     """A transform/solver plan for maps of one (nside, lmax), owning its workspace."""
 
-    def __init__(self, nside: int, lmax: int, nmaps: int = 1, device=None):
+    def __init__(self, nside: int, lmax: int, nmaps: int = 1, device=None, precision: int = FP64):
         lib = load()
         self.nside, self.lmax, self.nmaps = int(nside), int(lmax), int(nmaps)
+        self.precision = int(precision)
         self.npix = 12 * self.nside * self.nside
         self.nalm = n_alm(self.lmax)
         dev = torch.device("cuda" if device is None else device)
         with torch.cuda.device(dev):
             h = ctypes.c_void_p()
-            desc = _PlanDesc(self.nside, self.lmax, self.nmaps, 0)
+            desc = _PlanDesc(self.nside, self.lmax, self.nmaps, self.precision)
             _check(lib.dmwf_plan_create(ctypes.byref(desc), ctypes.byref(h)), "dmwf_plan_create")
             self._h = h
             nb = ctypes.c_size_t()
@@ -199,7 +203,7 @@ class Plan:
               eps_coarse: float = 1e-4, max_iter: int = 1_000_000, replay=None,
               start_final: bool = False, alm: torch.Tensor | None = None,
               out_map: torch.Tensor | None = None, want_residual: bool = False,
-              raise_on_cap: bool = False, cap_levels: int = 512):
+              raise_on_cap: bool = False, cap_levels: int = 512, eps_reduced: float = -1.0):
         alm = self._alm(alm)
         out_map = self._map(out_map)
         rep = None
@@ -208,12 +212,13 @@ class Plan:
         sc = _Schedule(float(beta), float(mu0), float(eps_final), float(eps_coarse),
                        int(max_iter), int(bool(start_final)),
                        ctypes.cast(rep, ctypes.POINTER(ctypes.c_int)) if rep is not None else None,
-                       len(replay) if replay is not None else 0, int(bool(want_residual)))
+                       len(replay) if replay is not None else 0, int(bool(want_residual)),
+                       float(eps_reduced))
         # one stats record per map
         nm = self.nmaps
         bufs = [((ctypes.c_int * cap_levels)(), (ctypes.c_double * cap_levels)(),
                  (ctypes.c_int * cap_levels)()) for _ in range(nm)]
-        sts = (_Stats * nm)(*[_Stats(0, 0, 0.0, 0.0, -1.0, cap_levels, *b) for b in bufs])
+        sts = (_Stats * nm)(*[_Stats(0, 0, 0.0, 0.0, -1.0, cap_levels, *b, 0) for b in bufs])
         status = load().dmwf_solve(self._h, _ptr(cl), _ptr(d), _ptr(ninv), ctypes.byref(sc),
                                    _ptr(alm), _ptr(out_map), sts,
                                    self.ws.data_ptr(), self.ws_bytes, _stream())
@@ -223,7 +228,7 @@ class Plan:
             nl = min(st.n_levels, cap_levels)
             out.append(SolveStats(st.n_levels, st.n_iter, st.alpha, st.final_cauchy,
                                   st.wf_residual, list(ipl[:nl]), list(xpl[:nl]),
-                                  list(lpl[:nl]), status))
+                                  list(lpl[:nl]), status, st.iters_reduced))
         return alm, out_map, (out[0] if nm == 1 else out)
 
     def autotune(self):

@@ -42,7 +42,7 @@ def test_host_side_validation_without_gpu():
     for nside, lmax, nmaps, prec, want in [(3, 4, 1, 0, 1), (0, 0, 1, 0, 1), (16384, 4, 1, 0, 1),
                                            (4, 12, 1, 0, 1), (4, -1, 1, 0, 1), (4, 8, 0, 0, 1),
                                            (4, 8, 65536, 0, 1),
-                                           (4, 8, 1, 1, 6)]:
+                                           (4, 8, 1, 3, 1)]:
         desc = b._PlanDesc(nside, lmax, nmaps, prec)
         assert lib.dmwf_plan_create(ctypes.byref(desc), ctypes.byref(h)) == want
         assert not h.value
