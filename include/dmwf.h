@@ -103,7 +103,8 @@ typedef struct {
                                 iterations without a 1% gain), then continues in
                                 FP64 down to eps_final; coarse levels run reduced
                                 throughout, and replayed solves never switch.
-                                <= 0 selects 1e-5 (FP32) or 1e-4 (BF16X3)      */
+                                <= 0 selects eps_final: the reduced iterations
+                                meet the final tolerance, FP64 ones confirm it */
 } dmwf_schedule;
 
 /* Per-solve statistics (host memory).  The three arrays are optional
@@ -201,6 +202,24 @@ dmwf_status dmwf_solve(dmwf_plan* plan, const double* dev_cl, const double* dev_
                        const double* dev_ninv, const dmwf_schedule* sched,
                        double* dev_alm_out, double* dev_map_out, dmwf_stats* stats,
                        void* dev_ws, size_t ws_bytes, void* stream);
+
+/* Several plans solved together, e.g. groups of maps of different Nside
+ * (Algorithm 2 for every map of every plan).  Plan i takes dev_cl[i],
+ * dev_d[i], dev_ninv[i], writes dev_alm_out[i] and dev_map_out[i], fills
+ * stats[i] (NULL, or its plan's nmaps records; stats itself may be NULL) and
+ * uses its own workspace dev_ws[i] of ws_bytes[i] bytes.  After the first,
+ * every iteration of every plan is one replay of a single HIP graph (the
+ * plans' launches one after another), and every map keeps its own device-side
+ * level control and stop; the host waits only once per batch of iterations.
+ * Every map comes out bit for bit as dmwf_solve on its own plan computes it.
+ * The schedule is shared; with replay_iters every map's schedule must have
+ * n_replay levels.  Plans and workspaces must be distinct (else
+ * DMWF_ERR_INVALID_ARG), 1 <= nplans <= 64; other errors as dmwf_solve. */
+dmwf_status dmwf_solve_plans(int nplans, dmwf_plan* const* plans, const double* const* dev_cl,
+                             const double* const* dev_d, const double* const* dev_ninv,
+                             const dmwf_schedule* sched, double* const* dev_alm_out,
+                             double* const* dev_map_out, dmwf_stats* const* stats,
+                             void* const* dev_ws, const size_t* ws_bytes, void* stream);
 
 /* Pick the tiles of the Legendre stages for this plan by timing each
  * candidate on the device.  Synthesis: ring pairs per lane {1, 2} x maps per

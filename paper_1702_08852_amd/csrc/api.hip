@@ -1243,45 +1243,61 @@ dmwf_status dmwf_wf_residual(dmwf_plan* p, const double* cl, const double* d, co
     return DMWF_OK;
 }
 
-dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
-                       const double* ninv_all, const dmwf_schedule* sc, double* alm_all,
-                       double* map_all, dmwf_stats* stats, void* ws, size_t ws_bytes,
-                       void* stream) {
-    if (!p || !cl_all || !d_all || !ninv_all || !sc || !alm_all || !map_all) {
-        set_error("NULL argument");
-        return DMWF_ERR_INVALID_ARG;
-    }
+}  // extern "C"
+
+namespace dmwf {
+namespace {
+
+// One plan's share of a solve: its inputs and outputs, its workspace, and the
+// host copies of its schedule.
+struct SolveJob {
+    dmwf_plan* p;
+    const double* cl;
+    const double* d;
+    const double* ninv;
+    double2* a;
+    double* map;
+    dmwf_stats* stats;
+    Ws W;
+    std::vector<double> alpha;
+    std::vector<std::vector<DevLevel>> lv;
+    int first_pix = 0;
+};
+
+dmwf_status check_schedule(const dmwf_schedule* sc) {
     const double beta = sc->beta > 0.0 ? sc->beta : 0.75;
     if (!(beta < 1.0) || !(sc->eps_final > 0.0) || !(sc->eps_coarse > 0.0) || sc->max_iter < 1 ||
         (sc->replay_iters && sc->n_replay < 1)) {
         set_error("schedule: need 0 < beta < 1, eps > 0, max_iter >= 1");
         return DMWF_ERR_INVALID_ARG;
     }
-    // the reduced contractions hand the last level over to FP64 below this ratio
-    const double eps_red = sc->eps_reduced > 0.0
-                               ? sc->eps_reduced
-                               : (p->prec == DMWF_BF16X3_GEMM ? 1e-4 : 1e-5);
+    return DMWF_OK;
+}
+
+// a0 (screening, alpha), a1 (every map's level schedule), the device control
+// blocks and the start residual of one plan; synchronizes the stream once.
+dmwf_status solve_setup(SolveJob& J, const dmwf_schedule* sc, hipStream_t s) {
+    dmwf_plan* p = J.p;
+    const Ws& W = J.W;
     const int nm = p->nmaps;
-    if (stats)
+    const int L = p->lmax;
+    const double sigma = 1.0 / p->omega;
+    const double beta = sc->beta > 0.0 ? sc->beta : 0.75;
+    // the reduced contractions hand the last level over to FP64 below this ratio
+    const double eps_red = sc->eps_reduced > 0.0 ? sc->eps_reduced : sc->eps_final;
+    if (J.stats)
         for (int k = 0; k < nm; ++k)
-            if (stats[k].cap_levels < 0) {
+            if (J.stats[k].cap_levels < 0) {
                 set_error("stats.cap_levels < 0");
                 return DMWF_ERR_INVALID_ARG;
             }
-    Ws W;
-    dmwf_status st = check_ws(p, ws, ws_bytes, &W);
-    if (st != DMWF_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int L = p->lmax;
-    const double sigma = 1.0 / p->omega;
-    double2* a = reinterpret_cast<double2*>(alm_all);
 
     // a0: screen the inputs and find alpha = 1 / max N^-1, every map at once
     {
         ProfScope ps(p, s, PROF_MISC);
         hipLaunchKernelGGL(k_set_ints, dim3(1), dim3(64), 0, s, W.flags(0), nm, 0);
-        hipLaunchKernelGGL(k_check, dim3(kCheckBlocks, nm), dim3(256), 0, s, d_all, ninv_all,
-                           p->npix, cl_all, L + 1, W.flags(0), W.bmax());
+        hipLaunchKernelGGL(k_check, dim3(kCheckBlocks, nm), dim3(256), 0, s, J.d, J.ninv,
+                           p->npix, J.cl, L + 1, W.flags(0), W.bmax());
         hipLaunchKernelGGL(k_max_final, dim3(nm), dim3(256), 0, s, W.bmax(), kCheckBlocks,
                            W.mdbl(0) + 2, 4);
     }
@@ -1292,10 +1308,10 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
     DMWF_HIP(hipMemcpyAsync(flags.data(), W.flags(0), nm * sizeof(int), hipMemcpyDeviceToHost, s));
     DMWF_HIP(hipMemcpyAsync(md.data(), W.mdbl(0), md.size() * sizeof(double),
                             hipMemcpyDeviceToHost, s));
-    DMWF_HIP(hipMemcpyAsync(hcl.data(), cl_all, hcl.size() * sizeof(double),
+    DMWF_HIP(hipMemcpyAsync(hcl.data(), J.cl, hcl.size() * sizeof(double),
                             hipMemcpyDeviceToHost, s));
     DMWF_HIP(hipStreamSynchronize(s));
-    std::vector<double> alpha(nm);
+    J.alpha.assign(nm, 0.0);
     for (int k = 0; k < nm; ++k) {
         if (flags[k]) {
             set_error("non-finite or negative values in d, N^-1 or C_l of map " +
@@ -1307,26 +1323,26 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
             set_error("every pixel of map " + std::to_string(k) + " is masked (N^-1 = 0)");
             return DMWF_ERR_INVALID_ARG;
         }
-        alpha[k] = 1.0 / wmax;
+        J.alpha[k] = 1.0 / wmax;
     }
 
     // a1: the level schedule of every map
-    std::vector<std::vector<DevLevel>> lv(nm);
+    J.lv.assign(nm, {});
     for (int k = 0; k < nm; ++k) {
         const double* cl = hcl.data() + (size_t)k * (L + 1);
         double clmax = 0.0;
         for (int l = 0; l <= L; ++l) clmax = std::max(clmax, cl[l]);
         std::vector<double> xis;
         if (sc->start_final) {
-            xis.push_back(alpha[k]);
+            xis.push_back(J.alpha[k]);
         } else {
             const double mu0 = sc->mu0 < 0.0 ? beta * clmax : sc->mu0;
-            double xi = alpha[k] + sigma * mu0;
-            while (xi > alpha[k] && (int)xis.size() <= kMaxLevels) {
+            double xi = J.alpha[k] + sigma * mu0;
+            while (xi > J.alpha[k] && (int)xis.size() <= kMaxLevels) {
                 xis.push_back(xi);
                 xi = beta * xi;
             }
-            xis.push_back(alpha[k]);
+            xis.push_back(J.alpha[k]);
         }
         const int nl = (int)xis.size();
         if (nl > kMaxLevels) {
@@ -1339,16 +1355,16 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
                       std::to_string(k) + " has " + std::to_string(nl));
             return DMWF_ERR_INVALID_ARG;
         }
-        lv[k].resize(nl);
+        J.lv[k].resize(nl);
         for (int i = 0; i < nl; ++i) {
-            const double xi = xis[i], mu = (xi - alpha[k]) / sigma;
+            const double xi = xis[i], mu = (xi - J.alpha[k]) / sigma;
             int ell = -1;
             for (int l = 0; l <= L; ++l)
                 if (cl[l] - mu > 0.0) ell = l;
-            lv[k][i] = DevLevel{xi,  mu, xi * p->omega, xi <= alpha[k] ? sc->eps_final : sc->eps_coarse,
-                                ell, 0,  sc->replay_iters ? sc->replay_iters[i] : 0, 0};
+            J.lv[k][i] = DevLevel{xi,  mu, xi * p->omega, xi <= J.alpha[k] ? sc->eps_final : sc->eps_coarse,
+                                  ell, 0,  sc->replay_iters ? sc->replay_iters[i] : 0, 0};
         }
-        for (int i = 0; i < nl; ++i) lv[k][i].ell_next = lv[k][std::min(i + 1, nl - 1)].ell;
+        for (int i = 0; i < nl; ++i) J.lv[k][i].ell_next = J.lv[k][std::min(i + 1, nl - 1)].ell;
     }
 
     // a1 / a6 on the device: the level tables and control blocks go to the
@@ -1357,16 +1373,16 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
     int nl_max = 1;
     for (int k = 0; k < nm; ++k) {
         DevCtrl c{};
-        c.nlev = (int)lv[k].size();
+        c.nlev = (int)J.lv[k].size();
         c.max_iter = sc->max_iter;
         c.replay = sc->replay_iters ? 1 : 0;
-        c.alpha = alpha[k];
+        c.alpha = J.alpha[k];
         c.reduced = p->prec != DMWF_FP64 ? 1 : 0;
         c.eps_reduced = eps_red;
         c.best = INFINITY;
         c0[k] = c;
         nl_max = std::max(nl_max, c.nlev);
-        DMWF_HIP(hipMemcpyAsync(W.levels(k), lv[k].data(), lv[k].size() * sizeof(DevLevel),
+        DMWF_HIP(hipMemcpyAsync(W.levels(k), J.lv[k].data(), J.lv[k].size() * sizeof(DevLevel),
                                 hipMemcpyHostToDevice, s));
     }
     DMWF_HIP(hipMemcpyAsync(W.ctrl(0), c0.data(), nm * sizeof(DevCtrl), hipMemcpyHostToDevice, s));
@@ -1381,56 +1397,64 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
     DMWF_HIP(hipGetLastError());
 
     // start: r = d on unmasked pixels (cold), or r = c (d - Y a0) at xi = alpha
-    int first_pix = 0;
     const RingMaps full = ring_full(p, W, nm);
+    dmwf_status st;
     if (sc->start_final) {
         {
             ProfScope ps(p, s, PROF_MISC);
-            hipLaunchKernelGGL(k_prep_syn, alm_grid(L, 256, nm), dim3(256), 0, s, a, p->nalm,
+            hipLaunchKernelGGL(k_prep_syn, alm_grid(L, 256, nm), dim3(256), 0, s, J.a, p->nalm,
                                p->d_g, W.ap(0), p->ws.alm_map, L);
         }
         st = leg_syn(p, W.ap(0), W.spec(0), LegMaps{nm, W.ell_full(), 0, nullptr}, s);
         if (st != DMWF_OK) return st;
         RingIO io{};
-        io.map_out = map_all;
+        io.map_out = J.map;
         io.pix_map = p->npix;
         st = launch_ring(p, RING_SYN, W.spec(0), full, io, s);
         if (st != DMWF_OK) return st;
         io = RingIO{};
-        io.map_in = map_all;
-        io.d = d_all;
-        io.w = ninv_all;
+        io.map_in = J.map;
+        io.d = J.d;
+        io.w = J.ninv;
         io.ctrl = W.ctrl(0);
         io.pix_map = p->npix;
         st = launch_ring(p, RING_ANA_CRES, W.spec(0), full, io, s);
         if (st != DMWF_OK) return st;
+        J.first_pix = 0;
     } else {
         {
             ProfScope ps(p, s, PROF_MISC);
-            hipLaunchKernelGGL(k_zero2, dim3(256), dim3(256), 0, s, a, (long long)nm * p->nalm);
+            hipLaunchKernelGGL(k_zero2, dim3(256), dim3(256), 0, s, J.a, (long long)nm * p->nalm);
         }
         RingIO io{};
-        io.d = d_all;
-        io.w = ninv_all;
+        io.d = J.d;
+        io.w = J.ninv;
         io.pix_map = p->npix;
         st = launch_ring(p, RING_ANA_FIRST, W.spec(0), full, io, s);
         if (st != DMWF_OK) return st;
-        first_pix = 1;
+        J.first_pix = 1;
     }
     DMWF_HIP(hipGetLastError());
+    return DMWF_OK;
+}
 
-    // After every iteration k_control takes each map's decision.  The host
-    // enqueues iterations in growing batches with two batches in flight and
-    // reads the control blocks once per batch, so the GPU never waits for the
-    // host; iterations enqueued after a map's stop do nothing for that map.
-    // Every iteration after the first is the same sequence of launches with
-    // the same arguments: it is captured once into a HIP graph (the ring
-    // stage's side-stream fork and join become graph branches) and replayed,
-    // which takes the per-launch host cost off the loop.  Timing events are
-    // not recorded by graph replays: with every launch timed (profiling level
-    // 1) the iterations are launched one by one; with the analysis timed
-    // (level 2) it is launched between its events and the rest of the
-    // iteration is replayed from a graph.
+// Every plan's iterations until every map of every plan has stopped.  After
+// each iteration k_control takes each map's decision.  The host enqueues
+// iterations in growing batches with two batches in flight and reads the
+// control blocks once per batch, so the GPU never waits for the host;
+// iterations enqueued after a map's stop do nothing for that map.  Every
+// iteration after the first is the same sequence of launches with the same
+// arguments: one HIP graph holds it for every plan (the plans one after
+// another; the ring stage's side-stream fork and join become graph branches)
+// and is replayed, which takes the per-launch host cost off the loop.  Timing
+// events are not recorded by graph replays: with every launch timed
+// (profiling level 1 on some plan) the iterations are launched one by one;
+// with the analysis timed (level 2) it is launched between its events and
+// the rest of the iteration is replayed from the graph.
+dmwf_status solve_loop(std::vector<SolveJob>& jobs, const dmwf_schedule* sc, hipStream_t s,
+                       std::vector<const DevCtrl*>& fin) {
+    bool any_prof1 = false;
+    for (auto& J : jobs) any_prof1 |= J.p->prof == 1;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     struct GraphGuard {
@@ -1445,49 +1469,69 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
             if (*g) (void)hipGraphDestroy(*g);
         }
     } guard{&graph, &gexec, s};
-    const bool split = p->prof == 2;
+    auto body = [&](SolveJob& J, hipStream_t st_) {
+        dmwf_plan* p = J.p;
+        return iterate_body(p, J.W, 0, p->nmaps, 0.0, 0.0, 0.0, J.cl, J.d, J.ninv, J.a, J.map,
+                            J.first_pix, nullptr, nullptr, J.W.ctrl(0), st_);
+    };
     auto one_iteration = [&]() -> dmwf_status {
-        if (first_pix || p->prof == 1) {
-            dmwf_status e = iterate_body(p, W, 0, nm, 0.0, 0.0, 0.0, cl_all, d_all, ninv_all, a,
-                                         map_all, first_pix, nullptr, nullptr, W.ctrl(0), s);
-            first_pix = 0;
-            return e;
+        bool first = false;
+        for (auto& J : jobs) first |= J.first_pix != 0;
+        if (first || any_prof1) {
+            for (auto& J : jobs) {
+                dmwf_status e = body(J, s);
+                J.first_pix = 0;
+                if (e != DMWF_OK) return e;
+            }
+            return DMWF_OK;
         }
         if (!gexec) {
-            // captured on the plan's own stream (the caller's may be the null
-            // stream, which cannot be captured), replayed on the caller's
-            hipStream_t cs = p->cap_stream;
+            // captured on the first plan's own stream (the caller's may be the
+            // null stream, which cannot be captured), replayed on the caller's
+            hipStream_t cs = jobs[0].p->cap_stream;
             DMWF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            dmwf_status e =
-                split ? iterate_rest(p, W, 0, nm, 0.0, 0.0, 0.0, cl_all, d_all, ninv_all, a,
-                                     map_all, 0, nullptr, nullptr, W.ctrl(0), cs)
-                      : iterate_body(p, W, 0, nm, 0.0, 0.0, 0.0, cl_all, d_all, ninv_all, a,
-                                     map_all, 0, nullptr, nullptr, W.ctrl(0), cs);
+            dmwf_status e = DMWF_OK;
+            for (auto& J : jobs) {
+                dmwf_plan* p = J.p;
+                e = p->prof == 2
+                        ? iterate_rest(p, J.W, 0, p->nmaps, 0.0, 0.0, 0.0, J.cl, J.d, J.ninv, J.a,
+                                       J.map, 0, nullptr, nullptr, J.W.ctrl(0), cs)
+                        : body(J, cs);
+                if (e != DMWF_OK) break;
+            }
             const hipError_t ce = hipStreamEndCapture(cs, &graph);
             if (e != DMWF_OK) return e;
             DMWF_HIP(ce);
             DMWF_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
         }
-        if (split) {
-            dmwf_status e = iterate_ana(p, W, 0, nm, W.ctrl(0), s);
-            if (e != DMWF_OK) return e;
-        }
+        for (auto& J : jobs)
+            if (J.p->prof == 2) {
+                dmwf_status e = iterate_ana(J.p, J.W, 0, J.p->nmaps, J.W.ctrl(0), s);
+                if (e != DMWF_OK) return e;
+            }
         DMWF_HIP(hipGraphLaunch(gexec, s));
         return DMWF_OK;
     };
+    hipEvent_t* bev = jobs[0].p->batch_ev;
     auto enqueue = [&](int nit, int slot) -> dmwf_status {
         for (int i = 0; i < nit; ++i) {
             dmwf_status e = one_iteration();
             if (e != DMWF_OK) return e;
         }
-        DMWF_HIP(hipMemcpyAsync(p->h_ctrl + (size_t)slot * nm, W.ctrl(0), nm * sizeof(DevCtrl),
-                                hipMemcpyDeviceToHost, s));
-        DMWF_HIP(hipEventRecord(p->batch_ev[slot], s));
+        for (auto& J : jobs) {
+            const int nm = J.p->nmaps;
+            DMWF_HIP(hipMemcpyAsync(J.p->h_ctrl + (size_t)slot * nm, J.W.ctrl(0),
+                                    nm * sizeof(DevCtrl), hipMemcpyDeviceToHost, s));
+        }
+        DMWF_HIP(hipEventRecord(bev[slot], s));
         return DMWF_OK;
     };
     auto all_done = [&](int slot) {
-        for (int k = 0; k < nm; ++k)
-            if (!p->h_ctrl[(size_t)slot * nm + k].done) return false;
+        for (auto& J : jobs) {
+            const int nm = J.p->nmaps;
+            for (int k = 0; k < nm; ++k)
+                if (!J.p->h_ctrl[(size_t)slot * nm + k].done) return false;
+        }
         return true;
     };
     // never more iterations than the cap allows, nor (replaying) than the
@@ -1502,7 +1546,7 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
     long long launched = 0;
     int batch = 4, cur = 0;
     int nb = (int)std::min<long long>(batch, budget);
-    st = enqueue(nb, cur);
+    dmwf_status st = enqueue(nb, cur);
     if (st != DMWF_OK) return st;
     launched += nb;
     bool whole[2] = {launched >= budget, false};  // snapshot taken after the whole budget
@@ -1513,9 +1557,9 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
         if (st != DMWF_OK) return st;
         launched += nb;
         whole[cur ^ 1] = launched >= budget;
-        DMWF_HIP(hipEventSynchronize(p->batch_ev[cur]));
+        DMWF_HIP(hipEventSynchronize(bev[cur]));
         if (all_done(cur)) {
-            DMWF_HIP(hipEventSynchronize(p->batch_ev[cur ^ 1]));
+            DMWF_HIP(hipEventSynchronize(bev[cur ^ 1]));
             cur ^= 1;
             break;
         }
@@ -1528,43 +1572,135 @@ dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
         }
         cur ^= 1;
     }
-    const DevCtrl* fin = p->h_ctrl + (size_t)cur * nm;
-    dmwf_status result = DMWF_OK;
+    fin.clear();
+    for (auto& J : jobs) fin.push_back(J.p->h_ctrl + (size_t)cur * J.p->nmaps);
+    return DMWF_OK;
+}
+
+// Statuses and statistics of one plan's maps after the loop.
+dmwf_status solve_finish(SolveJob& J, const dmwf_schedule* sc, const DevCtrl* fin, hipStream_t s,
+                         dmwf_status* result) {
+    dmwf_plan* p = J.p;
+    const int nm = p->nmaps;
     for (int k = 0; k < nm; ++k) {
         if (fin[k].status == 2) {
             set_error("Cauchy ratio of map " + std::to_string(k) + " is NaN");
             return DMWF_ERR_NONFINITE;
         }
-        if (fin[k].status == 1) result = DMWF_ERR_NOT_CONVERGED;
+        if (fin[k].status == 1) *result = DMWF_ERR_NOT_CONVERGED;
     }
-    if (stats) {
-        for (int k = 0; k < nm; ++k) {
-            dmwf_stats& S = stats[k];
-            const int nlev = fin[k].level + 1;
-            std::vector<int> its(lv[k].size(), 0);
-            DMWF_HIP(hipMemcpy(its.data(), W.lev_iters(k), its.size() * sizeof(int),
-                               hipMemcpyDeviceToHost));
-            for (int i = 0; i < nlev && i < S.cap_levels; ++i) {
-                if (S.iters_per_level) S.iters_per_level[i] = its[i];
-                if (S.xi_per_level) S.xi_per_level[i] = lv[k][i].xi;
-                if (S.lmax_per_level) S.lmax_per_level[i] = lv[k][i].ell;
-            }
-            S.n_levels = nlev;
-            S.n_iter = fin[k].total;
-            S.iters_reduced = fin[k].it_reduced;
-            S.alpha = alpha[k];
-            S.final_cauchy = fin[k].ratio;
-            S.wf_residual = -1.0;
-            if (sc->want_residual) {
-                double res = 0.0;
-                st = residual_map(p, W, cl_all + (size_t)k * (L + 1), d_all + (size_t)k * p->npix,
-                                  ninv_all + (size_t)k * p->npix, a + (size_t)k * p->nalm, &res, s);
-                if (st != DMWF_OK) return st;
-                S.wf_residual = res;
-            }
+    if (!J.stats) return DMWF_OK;
+    const int L = p->lmax;
+    for (int k = 0; k < nm; ++k) {
+        dmwf_stats& S = J.stats[k];
+        const int nlev = fin[k].level + 1;
+        std::vector<int> its(J.lv[k].size(), 0);
+        DMWF_HIP(hipMemcpy(its.data(), J.W.lev_iters(k), its.size() * sizeof(int),
+                           hipMemcpyDeviceToHost));
+        for (int i = 0; i < nlev && i < S.cap_levels; ++i) {
+            if (S.iters_per_level) S.iters_per_level[i] = its[i];
+            if (S.xi_per_level) S.xi_per_level[i] = J.lv[k][i].xi;
+            if (S.lmax_per_level) S.lmax_per_level[i] = J.lv[k][i].ell;
+        }
+        S.n_levels = nlev;
+        S.n_iter = fin[k].total;
+        S.iters_reduced = fin[k].it_reduced;
+        S.alpha = J.alpha[k];
+        S.final_cauchy = fin[k].ratio;
+        S.wf_residual = -1.0;
+        if (sc->want_residual) {
+            double res = 0.0;
+            dmwf_status st = residual_map(p, J.W, J.cl + (size_t)k * (L + 1),
+                                          J.d + (size_t)k * p->npix, J.ninv + (size_t)k * p->npix,
+                                          J.a + (size_t)k * p->nalm, &res, s);
+            if (st != DMWF_OK) return st;
+            S.wf_residual = res;
         }
     }
+    return DMWF_OK;
+}
+
+dmwf_status solve_jobs(std::vector<SolveJob>& jobs, const dmwf_schedule* sc, hipStream_t s) {
+    for (auto& J : jobs) {
+        dmwf_status st = solve_setup(J, sc, s);
+        if (st != DMWF_OK) return st;
+    }
+    std::vector<const DevCtrl*> fin;
+    dmwf_status st = solve_loop(jobs, sc, s, fin);
+    if (st != DMWF_OK) return st;
+    dmwf_status result = DMWF_OK;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        st = solve_finish(jobs[i], sc, fin[i], s, &result);
+        if (st != DMWF_OK) return st;
+    }
     return result;
+}
+
+}  // namespace
+}  // namespace dmwf
+
+extern "C" {
+
+dmwf_status dmwf_solve(dmwf_plan* p, const double* cl_all, const double* d_all,
+                       const double* ninv_all, const dmwf_schedule* sc, double* alm_all,
+                       double* map_all, dmwf_stats* stats, void* ws, size_t ws_bytes,
+                       void* stream) {
+    if (!p || !cl_all || !d_all || !ninv_all || !sc || !alm_all || !map_all) {
+        set_error("NULL argument");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    dmwf_status st = check_schedule(sc);
+    if (st != DMWF_OK) return st;
+    std::vector<SolveJob> jobs(1);
+    SolveJob& J = jobs[0];
+    J.p = p;
+    J.cl = cl_all;
+    J.d = d_all;
+    J.ninv = ninv_all;
+    J.a = reinterpret_cast<double2*>(alm_all);
+    J.map = map_all;
+    J.stats = stats;
+    st = check_ws(p, ws, ws_bytes, &J.W);
+    if (st != DMWF_OK) return st;
+    return solve_jobs(jobs, sc, static_cast<hipStream_t>(stream));
+}
+
+dmwf_status dmwf_solve_plans(int nplans, dmwf_plan* const* plans, const double* const* cl,
+                             const double* const* d, const double* const* ninv,
+                             const dmwf_schedule* sc, double* const* alm_out,
+                             double* const* map_out, dmwf_stats* const* stats, void* const* ws,
+                             const size_t* ws_bytes, void* stream) {
+    if (nplans < 1 || nplans > 64 || !plans || !cl || !d || !ninv || !sc || !alm_out ||
+        !map_out || !ws || !ws_bytes) {
+        set_error("NULL argument, or nplans outside 1..64");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    dmwf_status st = check_schedule(sc);
+    if (st != DMWF_OK) return st;
+    std::vector<SolveJob> jobs(nplans);
+    for (int i = 0; i < nplans; ++i) {
+        if (!plans[i] || !cl[i] || !d[i] || !ninv[i] || !alm_out[i] || !map_out[i]) {
+            set_error("NULL argument for plan " + std::to_string(i));
+            return DMWF_ERR_INVALID_ARG;
+        }
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i] || ws[j] == ws[i]) {
+                set_error("plans " + std::to_string(j) + " and " + std::to_string(i) +
+                          " share a plan or a workspace");
+                return DMWF_ERR_INVALID_ARG;
+            }
+        SolveJob& J = jobs[i];
+        J.p = plans[i];
+        J.cl = cl[i];
+        J.d = d[i];
+        J.ninv = ninv[i];
+        J.a = reinterpret_cast<double2*>(alm_out[i]);
+        J.map = map_out[i];
+        J.stats = stats ? stats[i] : nullptr;
+        st = check_ws(plans[i], ws[i], ws_bytes[i], &J.W);
+        if (st != DMWF_OK) return st;
+    }
+    return solve_jobs(jobs, sc, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -148,10 +148,11 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn_mx(SynArgs a) {
             for (int l0 = cb; l0 <= cend; l0 += kLegB) {
                 if (l0 <= hi) inject<K>(l0, ls, s0, s1, p1, p2);
                 if constexpr (P == DMWF_FP32_GEMM) {
+                    // whole blocks: the coefficients beyond l_iter are zero, and
+                    // the recurrence tables are padded past the last row
 #pragma unroll
                     for (int jj = 0; jj < kLegB / 2; ++jj) {
                         const int l = l0 + 2 * jj;
-                        if (l > ell) break;
                         const double Ae = A[l], Ao = A[l + 1];
                         float be[NP], bo[NP];
 #pragma unroll

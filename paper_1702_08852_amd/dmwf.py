@@ -73,6 +73,9 @@ def load() -> ctypes.CDLL:
     lib.dmwf_dm_iterate.argtypes = [vp, cd, cd, vp, vp, vp, vp, vp, vp, ci, vp, sz, vp]
     lib.dmwf_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(_Schedule), vp, vp,
                                ctypes.POINTER(_Stats), vp, sz, vp]
+    P = ctypes.POINTER
+    lib.dmwf_solve_plans.argtypes = [ci, P(vp), P(vp), P(vp), P(vp), P(_Schedule), P(vp), P(vp),
+                                     P(P(_Stats)), P(vp), P(sz), vp]
     lib.dmwf_autotune.argtypes = [vp, vp, sz, vp, ctypes.POINTER(ci), ctypes.POINTER(ctypes.c_float)]
     lib.dmwf_set_tiles.argtypes = [vp, ci, ci, ci, ci]
     lib.dmwf_set_pipeline.argtypes = [vp, ci]
@@ -206,30 +209,15 @@ class Plan:
               raise_on_cap: bool = False, cap_levels: int = 512, eps_reduced: float = -1.0):
         alm = self._alm(alm)
         out_map = self._map(out_map)
-        rep = None
-        if replay is not None:
-            rep = (ctypes.c_int * len(replay))(*[int(v) for v in replay])
-        sc = _Schedule(float(beta), float(mu0), float(eps_final), float(eps_coarse),
-                       int(max_iter), int(bool(start_final)),
-                       ctypes.cast(rep, ctypes.POINTER(ctypes.c_int)) if rep is not None else None,
-                       len(replay) if replay is not None else 0, int(bool(want_residual)),
-                       float(eps_reduced))
-        # one stats record per map
-        nm = self.nmaps
-        bufs = [((ctypes.c_int * cap_levels)(), (ctypes.c_double * cap_levels)(),
-                 (ctypes.c_int * cap_levels)()) for _ in range(nm)]
-        sts = (_Stats * nm)(*[_Stats(0, 0, 0.0, 0.0, -1.0, cap_levels, *b, 0) for b in bufs])
+        sc, keep = _schedule(beta, mu0, eps_final, eps_coarse, max_iter, replay, start_final,
+                             want_residual, eps_reduced)
+        sts, bufs = _stats(self.nmaps, cap_levels)
         status = load().dmwf_solve(self._h, _ptr(cl), _ptr(d), _ptr(ninv), ctypes.byref(sc),
                                    _ptr(alm), _ptr(out_map), sts,
                                    self.ws.data_ptr(), self.ws_bytes, _stream())
         _check(status, "dmwf_solve", allow=() if raise_on_cap else (ERR_NOT_CONVERGED,))
-        out = []
-        for st, (ipl, xpl, lpl) in zip(sts, bufs):
-            nl = min(st.n_levels, cap_levels)
-            out.append(SolveStats(st.n_levels, st.n_iter, st.alpha, st.final_cauchy,
-                                  st.wf_residual, list(ipl[:nl]), list(xpl[:nl]),
-                                  list(lpl[:nl]), status, st.iters_reduced))
-        return alm, out_map, (out[0] if nm == 1 else out)
+        out = _read_stats(sts, bufs, cap_levels, status)
+        return alm, out_map, (out[0] if self.nmaps == 1 else out)
 
     def autotune(self):
         """Time the Legendre tiles on this plan's shape and keep the fastest.
@@ -282,6 +270,66 @@ class Plan:
         _check(load().dmwf_profile_read(self._h, ctypes.byref(n), names, counts, ms),
                "dmwf_profile_read")
         return {names[i].decode(): (int(counts[i]), float(ms[i])) for i in range(n.value)}
+
+
+def _schedule(beta, mu0, eps_final, eps_coarse, max_iter, replay, start_final, want_residual,
+              eps_reduced):
+    rep = None
+    if replay is not None:
+        rep = (ctypes.c_int * len(replay))(*[int(v) for v in replay])
+    sc = _Schedule(float(beta), float(mu0), float(eps_final), float(eps_coarse),
+                   int(max_iter), int(bool(start_final)),
+                   ctypes.cast(rep, ctypes.POINTER(ctypes.c_int)) if rep is not None else None,
+                   len(replay) if replay is not None else 0, int(bool(want_residual)),
+                   float(eps_reduced))
+    return sc, rep
+
+
+def _stats(nm, cap_levels):
+    bufs = [((ctypes.c_int * cap_levels)(), (ctypes.c_double * cap_levels)(),
+             (ctypes.c_int * cap_levels)()) for _ in range(nm)]
+    sts = (_Stats * nm)(*[_Stats(0, 0, 0.0, 0.0, -1.0, cap_levels, *b, 0) for b in bufs])
+    return sts, bufs
+
+
+def _read_stats(sts, bufs, cap_levels, status):
+    out = []
+    for st, (ipl, xpl, lpl) in zip(sts, bufs):
+        nl = min(st.n_levels, cap_levels)
+        out.append(SolveStats(st.n_levels, st.n_iter, st.alpha, st.final_cauchy,
+                              st.wf_residual, list(ipl[:nl]), list(xpl[:nl]),
+                              list(lpl[:nl]), status, st.iters_reduced))
+    return out
+
+
+def solve_plans(plans, cls, ds, ninvs, beta: float = 0.75, mu0: float = -1.0,
+                eps_final: float = 1e-6, eps_coarse: float = 1e-4, max_iter: int = 1_000_000,
+                replay=None, want_residual: bool = False, raise_on_cap: bool = False,
+                cap_levels: int = 512, eps_reduced: float = -1.0):
+    """dmwf_solve_plans: every plan's maps solved together (one graph for all
+    plans' iterations).  Returns [(alm, map, stats)] per plan, stats as
+    Plan.solve returns them."""
+    n = len(plans)
+    vp, P = ctypes.c_void_p, ctypes.POINTER
+    alms = [pl._alm() for pl in plans]
+    maps = [pl._map() for pl in plans]
+    arr = lambda xs: (vp * n)(*xs)
+    sc, keep = _schedule(beta, mu0, 0.0 + eps_final, eps_coarse, max_iter, replay, False,
+                         want_residual, eps_reduced)
+    st_bufs = [_stats(pl.nmaps, cap_levels) for pl in plans]
+    st_ptrs = (P(_Stats) * n)(*[ctypes.cast(sb[0], P(_Stats)) for sb in st_bufs])
+    wsb = (ctypes.c_size_t * n)(*[pl.ws_bytes for pl in plans])
+    status = load().dmwf_solve_plans(
+        n, arr([pl._h.value for pl in plans]), arr([_ptr(x) for x in cls]),
+        arr([_ptr(x) for x in ds]), arr([_ptr(x) for x in ninvs]), ctypes.byref(sc),
+        arr([_ptr(x) for x in alms]), arr([_ptr(x) for x in maps]), st_ptrs,
+        arr([pl.ws.data_ptr() for pl in plans]), wsb, _stream())
+    _check(status, "dmwf_solve_plans", allow=() if raise_on_cap else (ERR_NOT_CONVERGED,))
+    res = []
+    for pl, a, m, (sts, bufs) in zip(plans, alms, maps, st_bufs):
+        out = _read_stats(sts, bufs, cap_levels, status)
+        res.append((a, m, out[0] if pl.nmaps == 1 else out))
+    return res
 
 
 def status_string(status: int) -> str:

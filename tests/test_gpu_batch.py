@@ -299,3 +299,70 @@ def test_plans_solving_at_once_from_threads():
     for (plan, args, alone), got in zip(jobs, out):
         np.testing.assert_array_equal(got[0].cpu().numpy(), alone[0].cpu().numpy())
         np.testing.assert_array_equal(got[1].cpu().numpy(), alone[1].cpu().numpy())
+
+
+# --------------------------------------------------------------------------
+# several plans (groups of different Nside) solved from one graph
+# --------------------------------------------------------------------------
+def _group(nside, n, first, prec=0):
+    from paper_1702_08852_amd import Plan
+    dev = device()
+    ps, T, ds = _members(nside, n, first)
+    plan = Plan(nside, ps[0].lmax, nmaps=n, device=dev, precision=prec)
+    st = lambda xs: torch_tensor(np.stack(xs) if n > 1 else xs[0], dev)
+    return plan, (st([p.cl for p in ps]), st(ds), st([p.ninv for p in ps]))
+
+
+@pytest.mark.parametrize("precs", [(0, 0, 0), (1, 0, 2)])
+def test_solve_plans_equals_each_plans_own_solve(precs):
+    """Three groups of the batched workload's recipe at Nside 4, 8 and 16 (in
+    FP64, or one group per precision form) iterate from one graph; every map
+    comes out bit for bit as its plan's own dmwf_solve gives it, with the same
+    counts per level, and the replayed form of the call too."""
+    from paper_1702_08852_amd import solve_plans
+    groups = [_group(4, 2, 0, precs[0]), _group(8, 3, 2, precs[1]), _group(16, 1, 5, precs[2])]
+    plans = [g[0] for g in groups]
+    cls, ds, ws = ([g[1][i] for g in groups] for i in range(3))
+    together = solve_plans(plans, cls, ds, ws, eps_final=1e-8, want_residual=True)
+    for (plan, args), (a, m, sts) in zip(groups, together):
+        a1, m1, st1 = plan.solve(*args, eps_final=1e-8, want_residual=True)
+        np.testing.assert_array_equal(a.cpu().numpy(), a1.cpu().numpy())
+        np.testing.assert_array_equal(m.cpu().numpy(), m1.cpu().numpy())
+        sts = sts if isinstance(sts, list) else [sts]
+        st1 = st1 if isinstance(st1, list) else [st1]
+        for s_, t_ in zip(sts, st1):
+            assert s_.status == 0 and s_.iters_per_level == t_.iters_per_level
+            assert s_.iters_reduced == t_.iters_reduced and s_.wf_residual == t_.wf_residual
+    # replayed: a mu0 small enough that every map's schedule is one coarse
+    # level and the last (beta xi_0 <= alpha), so the counts fit every map
+    mu0 = 0.5 * min(float(1.0 / w.max()) * 0.25 / (0.75 * 12 * pl.nside ** 2 / (4 * np.pi))
+                    for pl, w in zip(plans, ws))
+    ref = [plan.solve(*args, eps_final=1e-8, eps_coarse=1e-4, mu0=mu0, replay=[3, 4])
+           for plan, args in groups]
+    rep = solve_plans(plans, cls, ds, ws, eps_final=1e-8, mu0=mu0, replay=[3, 4])
+    for (a1, m1, _), (a, m, _) in zip(ref, rep):
+        np.testing.assert_array_equal(a.cpu().numpy(), a1.cpu().numpy())
+        np.testing.assert_array_equal(m.cpu().numpy(), m1.cpu().numpy())
+
+
+def test_solve_plans_with_analysis_timing_and_argument_errors():
+    """Kernel timing of the analysis on one plan (launched between its events,
+    the rest from the graph) changes no bits; a plan given twice is refused
+    before any work."""
+    from paper_1702_08852_amd import DmwfError, solve_plans
+    from paper_1702_08852_amd import dmwf as b
+    g1, g2 = _group(8, 2, 0), _group(16, 1, 3)
+    base = solve_plans([g1[0], g2[0]], [g1[1][0], g2[1][0]], [g1[1][1], g2[1][1]],
+                       [g1[1][2], g2[1][2]], eps_final=1e-8)
+    g2[0].profile(2)
+    timed = solve_plans([g1[0], g2[0]], [g1[1][0], g2[1][0]], [g1[1][1], g2[1][1]],
+                        [g1[1][2], g2[1][2]], eps_final=1e-8)
+    prof = g2[0].profile_read()
+    g2[0].profile(False)
+    assert prof["legendre_analysis"][0] > 0
+    for (a, m, _), (a1, m1, _) in zip(base, timed):
+        np.testing.assert_array_equal(a.cpu().numpy(), a1.cpu().numpy())
+        np.testing.assert_array_equal(m.cpu().numpy(), m1.cpu().numpy())
+    with pytest.raises(DmwfError) as e:
+        solve_plans([g1[0], g1[0]], [g1[1][0]] * 2, [g1[1][1]] * 2, [g1[1][2]] * 2)
+    assert e.value.status == b.ERR_INVALID_ARG
