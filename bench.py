@@ -13,9 +13,10 @@ the dominant kernel measured with HIP events around each of its launches on
 the launch stream, and the CPU oracle on a bounded sample.  Further records:
 configuration 3 with the Legendre contractions in FP32 and split-BF16x3 on the
 matrix cores; the solves and pair rates of configurations 1 and 2 (Nside 16
-and 256) with the oracle beside them; and the batched workload (96 maps of
+and 256) with the oracle beside them; the batched workload (96 maps of
 Nside 128, 256 and 512, one plan per Nside, the three solved from one graph)
-in the three precision forms.
+in the three precision forms; and the learned warm start against the cold
+start on 16 unseen Nside-512 maps.
 """
 from __future__ import annotations
 
@@ -420,6 +421,30 @@ def precision_legs(nside, lmax, cl, d, w, alm64, smap64, pairs, eps_final, eps_c
     return out
 
 
+def learned_warm_start(dev):
+    """The learned warm start on its evaluation workload (16 unseen Nside-512
+    maps of configuration 2's shape, eps_final 1e-6): cold solves against
+    solves entering from the network's estimate at the last level and at the
+    first level of the cooling schedule.  The network is the committed one,
+    trained by the library's own kernels on 2000 Nside-256 solves (its
+    training record is in profiles/)."""
+    from paper_1702_08852_amd import warmstart
+
+    path = warmstart.DEFAULT_WEIGHTS
+    if not os.path.exists(path):
+        return None
+    net = warmstart.load_net(path, dev)
+    log = lambda msg: print(f"warm start {msg}", file=sys.stderr, flush=True)
+    rec = warmstart.evaluate(net, dev, log=log)
+    rec["network"] = "24 -> 128 -> 128 -> 2, FP32, per (l, m) mode"
+    train = os.path.join(ROOT, "profiles", "warmstart_training_nside256_2000maps.md")
+    if os.path.exists(train):
+        for line in open(train):
+            if line.startswith("training_json:"):
+                rec["training_record"] = json.loads(line.split(":", 1)[1])
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -437,6 +462,8 @@ def main():
                     help="skip configurations 1 and 2 (Nside 16 and 256)")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip configuration 3's reduced-precision forms")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned warm start's evaluation")
     ap.add_argument("--batch-only", action="store_true",
                     help="only run the batched workload and print its record")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -647,6 +674,8 @@ def main():
         out["configs"] = bench_configs(dev, not args.no_cpu)
     if not args.no_batch:
         out["batched"] = bench_batch(dev, 20)
+    if not args.no_learned:
+        out["learned_warm_start"] = learned_warm_start(dev)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(nside, lmax, iters, args.cpu_fraction)
     print(json.dumps(out))

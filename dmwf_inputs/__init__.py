@@ -233,9 +233,16 @@ CONFIGS = {
     "cfg3": 3,   # Nside 1024, lmax 2048: as cfg2, sigma0 45 uK, 20% masked (band + 2000 holes of 0.3 deg)
     "cfg4": 4,   # batch member: damped spectrum, own |b| cut 5-20 deg + 50-500 holes of 1 deg,
                  # sigma0 ~ U[10, 60] uK times a lognormal(0, 0.25) per-pixel modulation
+    "cfg5": 5,   # warm-start training / evaluation map: configuration 2's shape (|b| < 15
+                 # + 200 holes of 1 deg, 30 uK ecliptic hits), its own holes and draws per index
 }
 
-DEFAULT_NSIDE = {"cfg1": 16, "cfg2": 256, "cfg3": 1024, "cfg4": 128}
+DEFAULT_NSIDE = {"cfg1": 16, "cfg2": 256, "cfg3": 1024, "cfg4": 128, "cfg5": 256}
+
+# Warm-start workload: training maps are cfg5 indices 0..1999 at Nside 256,
+# evaluation maps the unseen indices from 100000 on at Nside 512.
+WARM_TRAIN_NSIDE, WARM_TRAIN_MAPS = 256, 2000
+WARM_EVAL_NSIDE, WARM_EVAL_MAPS, WARM_EVAL_FIRST = 512, 16, 100000
 
 # The batched workload: maps per Nside (lmax = 2 Nside), 96 in all.
 BATCH_GROUPS = ((128, 48), (256, 32), (512, 16))
@@ -275,12 +282,12 @@ def make_problem(name: str, nside: int | None = None, lmax: int | None = None,
         mask = band_mask(nside, 10.0) | hole_mask(nside, 10, 5.0, r_hol)
         eps = 1e-8
         meta.update(bcut_deg=10.0, holes=10, hole_deg=5.0, noise="lognormal(0,0.5)")
-    elif name in ("cfg2", "cfg3"):
+    elif name in ("cfg2", "cfg3", "cfg5"):
         cl = cl_damped(lmax)
-        sigma0 = 30.0 if name == "cfg2" else 45.0
+        sigma0 = 45.0 if name == "cfg3" else 30.0
         hits = 1.0 + 4.0 * ecliptic_cos2(nside)
         sigma = sigma0 / np.sqrt(hits)
-        if name == "cfg2":
+        if name in ("cfg2", "cfg5"):
             mask = band_mask(nside, 15.0) | hole_mask(nside, 200, 1.0, r_hol)
             meta.update(bcut_deg=15.0, holes=200, hole_deg=1.0)
         else:
@@ -314,6 +321,18 @@ def random_alm(lmax: int, seed: int, cl: np.ndarray | None = None) -> np.ndarray
     if cl is None:
         cl = np.ones(lmax + 1)
     return draw_alm(cl, rng)
+
+
+def nn_init_params(seed: int) -> np.ndarray:
+    """Initial parameters of the warm-start network (flat FP32, layout W1 [24][128],
+    b1, W2 [128][128], b2, W3 [128][2], b3): He-normal weights, zero biases,
+    the output layer scaled down by 10."""
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_BASE, 79, seed]))
+    parts = []
+    for fan_in, fan_out, scale in ((24, 128, 1.0), (128, 128, 1.0), (128, 2, 0.1)):
+        parts.append(rng.standard_normal(fan_in * fan_out) * math.sqrt(2.0 / fan_in) * scale)
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
 
 
 def random_map(nside: int, seed: int) -> np.ndarray:

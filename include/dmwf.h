@@ -97,6 +97,10 @@ typedef struct {
                                 iterations on level k (n_replay = level count)    */
     int n_replay;
     int want_residual;       /* 1: compute stats.wf_residual (two extra transforms) */
+    int warm_start;          /* 1: start the cooling schedule (from level 0, or
+                                the last level with start_final) from the a_lm
+                                given in alm_out instead of a = 0; the first
+                                residual is c (d - Y a) at that level's xi    */
     double eps_reduced;      /* reduced-precision plans: the last level runs the
                                 matrix-core contractions until the Cauchy ratio
                                 falls below this (or stops improving: 64
@@ -273,6 +277,57 @@ dmwf_status dmwf_wf_residual(dmwf_plan* plan, const double* dev_cl, const double
 dmwf_status dmwf_profile_enable(dmwf_plan* plan, int enable);
 dmwf_status dmwf_profile_read(dmwf_plan* plan, int* n_classes, const char** names,
                               long* counts, double* total_ms);
+
+/* ---- Learned warm start -------------------------------------------------
+ * A per-mode harmonic-space network estimates the Wiener filter a_lm of a
+ * map from its masked data, as the starting point of a solve (the paper's
+ * solver starts from zero, Algorithm 2's initialisation; a warm start enters
+ * through dmwf_schedule.warm_start or start_final).  Architecture: F = 24
+ * features of one mode (l, m) -> 128 -> 128 -> 2, ReLU after the first two
+ * layers, FP32.  Features of mode (l, m), with d_lm = Omega Y^H (masked data)
+ * (dmwf_adjoint with the pixel area) and the map's white-noise level N_w:
+ *   0..17  d_{l+k, m} / sqrt(C_l + N_w), k = -4..4, re and im (0 outside
+ *          m <= l+k <= lmax; Im 0 for m = 0)
+ *   18 C_l / (C_l + N_w)   19 m / (l + 1)   20 sky fraction
+ *   21 log10(N_w / C_l) / 10   22, 23 zero
+ * Output: a_lm = sqrt(C_l) (y0 + i y1); modes with l < 2 or C_l = 0 get 0.
+ * Parameters are one flat FP32 vector: W1 [24][128], b1 [128], W2 [128][128],
+ * b2 [128], W3 [128][2], b3 [2] (row-major, y = x W + b).  Training minimises
+ * the mean over a batch of |y - t|^2 (t the whitened Wiener filter a_lm) with
+ * Adam (beta 0.9, 0.999, eps 1e-8).  All device pointers are caller-owned;
+ * the network owns its parameters, optimizer state and activation buffers
+ * for batches up to max_batch rows.  One call at a time per network. */
+typedef struct dmwf_nn dmwf_nn;
+int dmwf_nn_param_count(void);
+/* Parameters zero until dmwf_nn_set_params. */
+dmwf_status dmwf_nn_create(int max_batch, dmwf_nn** out);
+void dmwf_nn_destroy(dmwf_nn* net);
+/* Copy the flat parameters out / in (device FP32); set also resets Adam. */
+dmwf_status dmwf_nn_get_params(dmwf_nn* net, float* dev_out, void* stream);
+dmwf_status dmwf_nn_set_params(dmwf_nn* net, const float* dev_in, void* stream);
+/* N_w = Omega / mean of N^-1 over unmasked pixels, and the unmasked sky
+ * fraction, of one map (synchronizes the stream). */
+dmwf_status dmwf_nn_noise_stats(const double* dev_ninv, long long npix, double* noise_w,
+                                double* fsky, void* stream);
+/* Feature rows [n][24] for the a_lm slots dev_slots[0..n-1] (NULL: slots
+ * 0..n-1) of one map; with dev_target (a Wiener filter a_lm) also the
+ * training targets [n][2]. */
+dmwf_status dmwf_nn_features(int lmax, const double* dev_dlm, const double* dev_cl,
+                             double noise_w, double fsky, const int* dev_slots, int n,
+                             const double* dev_target, float* dev_x, float* dev_t, void* stream);
+/* y [n][2] = network(x [n][24]), n <= max_batch. */
+dmwf_status dmwf_nn_forward(dmwf_nn* net, const float* dev_x, int n, float* dev_y, void* stream);
+/* Gradient of the batch loss with respect to the flat parameters into
+ * dev_grad, the loss into dev_loss[0]; parameters unchanged. */
+dmwf_status dmwf_nn_gradient(dmwf_nn* net, const float* dev_x, const float* dev_t, int n,
+                             float* dev_grad, float* dev_loss, void* stream);
+/* One Adam step on the batch (loss before the step into dev_loss[0]). */
+dmwf_status dmwf_nn_train_step(dmwf_nn* net, const float* dev_x, const float* dev_t, int n,
+                               float lr, float* dev_loss, void* stream);
+/* The network's estimate of every a_lm of one map into dev_alm_out [n_alm][2]. */
+dmwf_status dmwf_nn_warm_start(dmwf_nn* net, int lmax, const double* dev_dlm,
+                               const double* dev_cl, double noise_w, double fsky,
+                               double* dev_alm_out, void* stream);
 
 /* Human-readable status and the last error message of the calling thread. */
 const char* dmwf_status_string(dmwf_status status);

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.environ.get("DMWF_BUILD_DIR", os.path.join(HERE, "_build"))
 LIB = os.environ.get("DMWF_LIB_OUT", os.path.join(HERE, "libdmwf.so"))
-SOURCES = ["api.hip", "legendre.hip", "legendre_mx.hip", "ring.hip"]
+SOURCES = ["api.hip", "legendre.hip", "legendre_mx.hip", "nn.hip", "ring.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -1396,10 +1396,11 @@ dmwf_status solve_setup(SolveJob& J, const dmwf_schedule* sc, hipStream_t s) {
     }
     DMWF_HIP(hipGetLastError());
 
-    // start: r = d on unmasked pixels (cold), or r = c (d - Y a0) at xi = alpha
+    // start: r = d on unmasked pixels (cold), or r = c (d - Y a0) at the xi of
+    // the first level (warm: alpha with start_final, else the cooling's xi_0)
     const RingMaps full = ring_full(p, W, nm);
     dmwf_status st;
-    if (sc->start_final) {
+    if (sc->start_final || sc->warm_start) {
         {
             ProfScope ps(p, s, PROF_MISC);
             hipLaunchKernelGGL(k_prep_syn, alm_grid(L, 256, nm), dim3(256), 0, s, J.a, p->nalm,

@@ -270,7 +270,8 @@ dmwf_status launch_leg_ana_mx(dmwf_plan* p, const double2* spec, double2* part, 
 
 // Ring stage modes.  SYN: F -> map.  ANA*: a pixel map -> G, the map being
 // map_in (ANA), d on unmasked pixels (ANA_FIRST), w (d - map_in) (ANA_RESID),
-// w d (ANA_WD) or c (d - map_in) with the pixel-step coefficient c (ANA_CRES).
+// w d (ANA_WD) or c (d - map_in) with the pixel-step coefficient c at the
+// control block's current xi (ANA_CRES).
 // ITER: F -> s (Cauchy sums, s_map updated) -> r = c (d - s) -> G.
 // SYN_WRES: F -> s (not stored) -> r = w (d - s) -> G.
 enum RingMode {
@@ -295,7 +296,7 @@ struct RingIO {
     // Per-map control blocks or NULL.  RING_ITER inside the solve loop takes
     // xi, alpha and the m bounds of the current and next level from them, and
     // nothing runs for a map whose solve has stopped; RING_ANA_CRES takes
-    // xi = alpha of each map.
+    // each map's current xi and alpha.
     const DevCtrl* ctrl;
     const int* mhi_tab;     // [maps][kMaxLevels][nq]
     long long pix_map;      // doubles between consecutive maps' pixel arrays

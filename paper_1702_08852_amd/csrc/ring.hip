@@ -354,8 +354,9 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     }
     const int ell = min(a.rm.ell_syn[map * a.rm.ell_stride], msyn);
     const int ella = min(a.rm.ell_ana[map * a.rm.ell_stride], mana);
-    // pixel step coefficients: the map's own in the solve loop
-    const double xi_ = ctrl ? (a.pix == PIX_CRES ? ctrl->alpha : ctrl->xi) : a.io.xi;
+    // pixel step coefficients: the map's own in the solve loop (the warm
+    // start's residual takes the xi of the level the solve starts on)
+    const double xi_ = ctrl ? ctrl->xi : a.io.xi;
     const double alpha_ = ctrl ? ctrl->alpha : a.io.alpha;
     const int tid = threadIdx.x;
     // m per thread and batch in the fold and unfold

@@ -39,7 +39,8 @@ class _Schedule(ctypes.Structure):
                 ("eps_final", ctypes.c_double), ("eps_coarse", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("start_final", ctypes.c_int),
                 ("replay_iters", ctypes.POINTER(ctypes.c_int)), ("n_replay", ctypes.c_int),
-                ("want_residual", ctypes.c_int), ("eps_reduced", ctypes.c_double)]
+                ("want_residual", ctypes.c_int), ("warm_start", ctypes.c_int),
+                ("eps_reduced", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -85,6 +86,20 @@ def load() -> ctypes.CDLL:
     lib.dmwf_profile_enable.argtypes = [vp, ci]
     lib.dmwf_profile_read.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ctypes.c_char_p),
                                       ctypes.POINTER(ctypes.c_long), ctypes.POINTER(cd)]
+    fp = ctypes.c_void_p
+    lib.dmwf_nn_param_count.restype = ci
+    lib.dmwf_nn_create.argtypes = [ci, ctypes.POINTER(vp)]
+    lib.dmwf_nn_destroy.argtypes = [vp]
+    lib.dmwf_nn_destroy.restype = None
+    lib.dmwf_nn_get_params.argtypes = [vp, fp, vp]
+    lib.dmwf_nn_set_params.argtypes = [vp, fp, vp]
+    lib.dmwf_nn_noise_stats.argtypes = [vp, ctypes.c_longlong, ctypes.POINTER(cd),
+                                        ctypes.POINTER(cd), vp]
+    lib.dmwf_nn_features.argtypes = [ci, vp, vp, cd, cd, vp, ci, vp, fp, fp, vp]
+    lib.dmwf_nn_forward.argtypes = [vp, fp, ci, fp, vp]
+    lib.dmwf_nn_gradient.argtypes = [vp, fp, fp, ci, fp, fp, vp]
+    lib.dmwf_nn_train_step.argtypes = [vp, fp, fp, ci, ctypes.c_float, fp, vp]
+    lib.dmwf_nn_warm_start.argtypes = [vp, ci, vp, vp, cd, cd, vp, vp]
     lib.dmwf_status_string.argtypes = [ci]
     lib.dmwf_status_string.restype = ctypes.c_char_p
     lib.dmwf_last_error.restype = ctypes.c_char_p
@@ -206,11 +221,14 @@ class Plan:
               eps_coarse: float = 1e-4, max_iter: int = 1_000_000, replay=None,
               start_final: bool = False, alm: torch.Tensor | None = None,
               out_map: torch.Tensor | None = None, want_residual: bool = False,
-              raise_on_cap: bool = False, cap_levels: int = 512, eps_reduced: float = -1.0):
+              raise_on_cap: bool = False, cap_levels: int = 512, eps_reduced: float = -1.0,
+              warm_start: bool = False):
+        """dmwf_solve.  start_final / warm_start: alm holds the starting a_lm
+        (the last level only, or the whole cooling schedule)."""
         alm = self._alm(alm)
         out_map = self._map(out_map)
         sc, keep = _schedule(beta, mu0, eps_final, eps_coarse, max_iter, replay, start_final,
-                             want_residual, eps_reduced)
+                             want_residual, eps_reduced, warm_start)
         sts, bufs = _stats(self.nmaps, cap_levels)
         status = load().dmwf_solve(self._h, _ptr(cl), _ptr(d), _ptr(ninv), ctypes.byref(sc),
                                    _ptr(alm), _ptr(out_map), sts,
@@ -273,7 +291,7 @@ class Plan:
 
 
 def _schedule(beta, mu0, eps_final, eps_coarse, max_iter, replay, start_final, want_residual,
-              eps_reduced):
+              eps_reduced, warm_start=False):
     rep = None
     if replay is not None:
         rep = (ctypes.c_int * len(replay))(*[int(v) for v in replay])
@@ -281,7 +299,7 @@ def _schedule(beta, mu0, eps_final, eps_coarse, max_iter, replay, start_final, w
                    int(max_iter), int(bool(start_final)),
                    ctypes.cast(rep, ctypes.POINTER(ctypes.c_int)) if rep is not None else None,
                    len(replay) if replay is not None else 0, int(bool(want_residual)),
-                   float(eps_reduced))
+                   int(bool(warm_start)), float(eps_reduced))
     return sc, rep
 
 
@@ -330,6 +348,104 @@ def solve_plans(plans, cls, ds, ninvs, beta: float = 0.75, mu0: float = -1.0,
         out = _read_stats(sts, bufs, cap_levels, status)
         res.append((a, m, out[0] if pl.nmaps == 1 else out))
     return res
+
+
+def _fptr(t):
+    if t is None:
+        return None
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("expected a contiguous float32 CUDA tensor")
+    return t.data_ptr()
+
+
+def _iptr(t):
+    if t is None:
+        return None
+    if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("expected a contiguous int32 CUDA tensor")
+    return t.data_ptr()
+
+
+N_FEATURES, N_OUT = 24, 2
+
+
+class Net:
+    """The warm-start network (dmwf_nn): FP32 parameters on the device."""
+
+    def __init__(self, max_batch: int = 65536, device=None):
+        lib = load()
+        dev = torch.device("cuda" if device is None else device)
+        with torch.cuda.device(dev):
+            h = ctypes.c_void_p()
+            _check(lib.dmwf_nn_create(int(max_batch), ctypes.byref(h)), "dmwf_nn_create")
+        self._h, self.device, self.max_batch = h, dev, int(max_batch)
+        self.n_params = int(lib.dmwf_nn_param_count())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().dmwf_nn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> torch.Tensor:
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _check(load().dmwf_nn_get_params(self._h, _fptr(out), _stream()), "dmwf_nn_get_params")
+        return out
+
+    def set_params(self, p: torch.Tensor) -> None:
+        if p.numel() != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        _check(load().dmwf_nn_set_params(self._h, _fptr(p), _stream()), "dmwf_nn_set_params")
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        n = x.shape[0]
+        y = torch.empty((n, N_OUT), dtype=torch.float32, device=self.device)
+        _check(load().dmwf_nn_forward(self._h, _fptr(x), n, _fptr(y), _stream()), "dmwf_nn_forward")
+        return y
+
+    def gradient(self, x: torch.Tensor, t: torch.Tensor):
+        g = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(load().dmwf_nn_gradient(self._h, _fptr(x), _fptr(t), x.shape[0], _fptr(g),
+                                       _fptr(loss), _stream()), "dmwf_nn_gradient")
+        return g, loss
+
+    def train_step(self, x: torch.Tensor, t: torch.Tensor, lr: float, loss: torch.Tensor):
+        _check(load().dmwf_nn_train_step(self._h, _fptr(x), _fptr(t), x.shape[0], float(lr),
+                                         _fptr(loss), _stream()), "dmwf_nn_train_step")
+
+    def warm_start(self, lmax: int, dlm: torch.Tensor, cl: torch.Tensor, noise_w: float,
+                   fsky: float) -> torch.Tensor:
+        out = torch.empty((n_alm(lmax), 2), dtype=torch.float64, device=self.device)
+        _check(load().dmwf_nn_warm_start(self._h, int(lmax), _ptr(dlm), _ptr(cl), float(noise_w),
+                                         float(fsky), _ptr(out), _stream()), "dmwf_nn_warm_start")
+        return out
+
+
+def noise_stats(ninv: torch.Tensor):
+    """(N_w, sky fraction) of one map: dmwf_nn_noise_stats."""
+    nw, fs = ctypes.c_double(), ctypes.c_double()
+    _check(load().dmwf_nn_noise_stats(_ptr(ninv), ninv.numel(), ctypes.byref(nw), ctypes.byref(fs),
+                                      _stream()), "dmwf_nn_noise_stats")
+    return nw.value, fs.value
+
+
+def nn_features(lmax: int, dlm: torch.Tensor, cl: torch.Tensor, noise_w: float, fsky: float,
+                slots: torch.Tensor | None = None, n: int | None = None,
+                target: torch.Tensor | None = None):
+    """Feature rows (and targets) of the listed a_lm slots: dmwf_nn_features."""
+    n = int(slots.numel()) if slots is not None else int(n if n is not None else n_alm(lmax))
+    x = torch.empty((n, N_FEATURES), dtype=torch.float32, device=dlm.device)
+    t = torch.empty((n, N_OUT), dtype=torch.float32, device=dlm.device) if target is not None else None
+    _check(load().dmwf_nn_features(int(lmax), _ptr(dlm), _ptr(cl), float(noise_w), float(fsky),
+                                   _iptr(slots), n, _ptr(target), _fptr(x), _fptr(t), _stream()),
+           "dmwf_nn_features")
+    return x, t
 
 
 def status_string(status: int) -> str:
