@@ -76,6 +76,7 @@ def cpu_baseline(nside, lmax, iters_per_solve, fraction):
     import oracle
 
     k = max(1, int(round(1.0 / fraction)))
+    cores = oracle.max_threads()
     z, st, nph, p0, start = oracle.rings(nside)
     nr = len(z)
     nalm = oracle.n_alm(lmax)
@@ -89,9 +90,9 @@ def cpu_baseline(nside, lmax, iters_per_solve, fraction):
     ana_all = (lmax + 1) * int(nph.sum()) + nr * nalm
     ana_smp = len(ms) * int(nph.sum()) + nr * sum(lmax - m + 1 for m in ms)
     t0 = time.perf_counter()
-    oracle.alm2map_rings(a, nside, lmax, rings)
+    oracle.alm2map_rings(a, nside, lmax, rings, nthreads=cores)
     t1 = time.perf_counter()
-    oracle.adjoint_m(mp, nside, lmax, ms)
+    oracle.adjoint_m(mp, nside, lmax, ms, nthreads=cores)
     t2 = time.perf_counter()
     pair_s = (t1 - t0) * syn_all / syn_smp + (t2 - t1) * ana_all / ana_smp
     # the same oracle on one thread, on every 64th ring and m, scaled the same way
@@ -104,6 +105,7 @@ def cpu_baseline(nside, lmax, iters_per_solve, fraction):
     t4 = time.perf_counter()
     oracle.adjoint_m(mp, nside, lmax, m1, nthreads=1)
     t5 = time.perf_counter()
+    oracle.adjoint_m(mp, nside, lmax, [0], nthreads=cores)  # the thread count back for later calls
     pair_1t = (t4 - t3) * syn_all / s1 + (t5 - t4) * ana_all / a1
     model = "unknown"
     try:
@@ -116,7 +118,7 @@ def cpu_baseline(nside, lmax, iters_per_solve, fraction):
     return {
         "value": 1.0 / (pair_s * iters_per_solve),
         "unit": "solves/s",
-        "cores": oracle.max_threads(),
+        "cores": cores,
         "kind": "oracle",
         "extrapolated": True,
         "cpu_model": model,
@@ -133,40 +135,38 @@ def cpu_baseline(nside, lmax, iters_per_solve, fraction):
     }
 
 
-TRAFFIC_FILES = {
-    "legendre_analysis": ("profiles/k_leg_ana_cfg3_nside1024_hbm_traffic.md",
-                          "paper_1702_08852_amd/csrc/legendre.hip"),
-    "legendre_synthesis": ("profiles/k_leg_syn_cfg3_nside1024_hbm_traffic.md",
-                           "paper_1702_08852_amd/csrc/legendre.hip"),
-}
+TRAFFIC_FILE = "profiles/hbm_traffic_fp64_nside1024_iteration.md"
+TRAFFIC_KERNELS = {"legendre_analysis": "k_leg_ana", "legendre_synthesis": "k_leg_syn",
+                   "ring_iter": "k_ring_fft", "harmonic_diag": "k_diag"}
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch from the committed counter summary of this kernel.
+    """HBM bytes per launch of a kernel class from the committed counter summary.
 
-    The summary holds a line 'traffic_json: {...}' with the calibrated bytes per
-    launch and the SHA-256 of the kernel's source file at the time the counters
-    were taken; if the source has changed since, the figure no longer describes
-    the kernel and None is returned.
+    The summary holds lines 'traffic_json: {...}' with the calibrated bytes per
+    launch of each kernel and the SHA-256 of its source file at the time the
+    counters were taken; if the source has changed since, the figure no longer
+    describes the kernel and None is returned.
     """
     import hashlib
 
-    ent = TRAFFIC_FILES.get(kernel)
-    if ent is None:
+    name = TRAFFIC_KERNELS.get(kernel)
+    summ = os.path.join(ROOT, TRAFFIC_FILE)
+    if name is None or not os.path.exists(summ):
         return None
-    summ, src = (os.path.join(ROOT, x) for x in ent)
-    if not (os.path.exists(summ) and os.path.exists(src)):
-        return None
-    rec = None
     for line in open(summ):
-        if line.startswith("traffic_json:"):
-            rec = json.loads(line.split(":", 1)[1])
-    if rec is None:
-        return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("source_sha256") != sha:
-        return None
-    return rec["bytes_per_launch"]
+        if not line.startswith("traffic_json:"):
+            continue
+        rec = json.loads(line.split(":", 1)[1])
+        if rec.get("kernel") != name:
+            continue
+        src = os.path.join(ROOT, rec["source"])
+        if not os.path.exists(src):
+            return None
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("source_sha256"):
+            return None
+        return rec["bytes_per_launch"]
+    return None
 
 
 def copy_calibration(dev):
@@ -445,6 +445,41 @@ def learned_warm_start(dev):
     return rec
 
 
+def probe(dev, nside, maps, precision, iters):
+    """A short fixed workload for profiler runs: `iters` full-band iterations
+    at xi = alpha (replayed, graph launches) of one plan of `maps` maps of
+    configuration 3's recipe at this Nside (the batched workload's recipe for
+    several maps), from a zero start."""
+    import numpy as np
+    import torch
+
+    import dmwf_inputs as inp
+    from paper_1702_08852_amd import BF16X3_GEMM, FP32_GEMM, FP64, Plan
+
+    prec = {"fp64": FP64, "fp32": FP32_GEMM, "bf16x3": BF16X3_GEMM}[precision]
+    if maps == 1:
+        probs = [inp.make_problem("cfg3", nside=nside)]
+    else:
+        probs = [inp.make_problem("cfg4", nside=nside, index=k) for k in range(maps)]
+    lmax = probs[0].lmax
+    plan = Plan(nside, lmax, nmaps=maps, device=dev, precision=prec)
+    if maps > 1:
+        plan.autotune()
+    st = lambda xs: torch.tensor(np.stack(xs) if maps > 1 else xs[0], device=dev).contiguous()
+    sig = plan.alm2map(st([q.alm_true for q in probs]))
+    d = (sig + st([q.sigma * q.white for q in probs])).masked_fill(st([q.mask for q in probs]), 0.0)
+    w, cl = st([q.ninv for q in probs]), st([q.cl for q in probs])
+    a0 = torch.zeros_like(plan._alm())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, sts = plan.solve(cl, d.contiguous(), w, eps_final=1e-6, start_final=True, alm=a0,
+                           replay=[iters])
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": {"nside": nside, "lmax": lmax, "maps": maps,
+                                "precision": precision, "iterations": iters,
+                                "seconds": time.perf_counter() - t0}}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -468,6 +503,12 @@ def main():
                     help="only run the batched workload and print its record")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--probe-iterations", type=int, default=0,
+                    help="only run this many full-band iterations (xi = alpha) of the plan "
+                         "shape given by --nside, --maps and --precision, for profiler runs")
+    ap.add_argument("--maps", type=int, default=1, help="maps of the --probe-iterations plan")
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32", "bf16x3"),
+                    help="Legendre contraction of the --probe-iterations plan")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this library "
@@ -479,6 +520,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.copy_calibration:
         copy_calibration(dev)
+        return
+    if args.probe_iterations > 0:
+        probe(dev, args.nside, args.maps, args.precision, args.probe_iterations)
         return
     if args.batch_only:
         print(json.dumps({"batched": bench_batch(dev, 20)}))
@@ -531,7 +575,20 @@ def main():
         roof = {"kernel": dom, "bound": "alu", "achieved": achieved,
                 "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": measured_traffic(dom),
-                "launches": cnt, "avg_launch_ms": tot_ms / cnt}
+                "launches": cnt, "avg_launch_ms": tot_ms / cnt,
+                "priced_on": "the full T(l_iter) of every launch (8 flops per triple)"}
+        # the same time priced on the work the kernel does: the triples after
+        # each ring's recurrence start (polar terms below 2^-100 skipped), and
+        # the lane-steps it issues (wave-wide starts, whole blocks)
+        key = "analysis_issued" if dom == "legendre_analysis" else "synthesis_issued"
+        work = {ell: plan.legendre_work(ell) for s in stats for ell in set(s.lmax_per_level)}
+        started = issued = 0
+        for s in stats:
+            for it, ell in zip(s.iters_per_level, s.lmax_per_level):
+                started += it * work[ell]["started"]
+                issued += it * work[ell][key]
+        roof["frac_started_work"] = 8.0 * started / (tot_ms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS
+        roof["frac_issued_work"] = 8.0 * issued / (tot_ms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS
     else:
         npix = 12 * nside * nside
         achieved = 32.0 * npix * cnt / (tot_ms * 1e-3) / 1e9
@@ -583,13 +640,18 @@ def main():
     torch.cuda.synchronize()
     dm_iterate_ms = e0.elapsed_time(e1) / 10
     f_full = legendre_flops(nside, lmax)
+    wfull = plan.legendre_work(lmax)
     leg = {}
-    for k in ("legendre_analysis", "legendre_synthesis"):
+    for k, key in (("legendre_analysis", "analysis_issued"),
+                   ("legendre_synthesis", "synthesis_issued")):
         c_, t_ = pprof[k]
         if c_:
+            sec = t_ / c_ * 1e-3
             leg[k] = {"avg_launch_ms": t_ / c_,
-                      "achieved_tflops": f_full / (t_ / c_ * 1e-3) / 1e12,
-                      "frac": f_full / (t_ / c_ * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS}
+                      "achieved_tflops": f_full / sec / 1e12,
+                      "frac": f_full / sec / 1e12 / FP64_VALU_PEAK_TFLOPS,
+                      "frac_started_work": 8.0 * wfull["started"] / sec / 1e12 / FP64_VALU_PEAK_TFLOPS,
+                      "frac_issued_work": 8.0 * wfull[key] / sec / 1e12 / FP64_VALU_PEAK_TFLOPS}
     pair_frac = 2 * f_full / (pair_ms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS
 
     resid = plan.wf_residual(cl, d, w, alm)

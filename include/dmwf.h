@@ -264,6 +264,16 @@ dmwf_status dmwf_wf_residual(dmwf_plan* plan, const double* dev_cl, const double
                              const double* dev_ninv, const double* dev_alm, double* host_out,
                              void* dev_ws, size_t ws_bytes, void* stream);
 
+/* Work of one FP64 Legendre launch at band limit ell (0..lmax), counted on
+ * the host from the plan's recurrence starts and its current tiles:
+ * out[0] = nq (ell+1)(ell+2)/2 triples (m, l, ring pair), the full work;
+ * out[1] = triples at or after each (m, ring pair)'s recurrence start (the
+ * polar terms below 2^-100 skipped); out[2] / out[3] = lane-steps the
+ * synthesis / analysis kernel issues (each a recurrence step and its
+ * contraction for one ring pair: wave-wide starts, whole blocks, idle slots
+ * skipped by the analysis).  Synchronizes the device on its first call. */
+dmwf_status dmwf_legendre_work(dmwf_plan* plan, int ell, long long* out);
+
 /* Kernel timing.  enable = 1: every launch is bracketed by HIP events on the
  * launch stream (the solve loop then launches every iteration kernel by
  * kernel).  enable = 2: only the Legendre analysis launches are (the solve

@@ -153,6 +153,7 @@ struct dmwf_plan {
     int* d_mhi_full = nullptr; // [nq] largest m with d_lsmin <= lmax, or -1
     double* d_s0 = nullptr; // mu at ls-1
     double* d_s1 = nullptr; // mu at ls
+    std::vector<int> h_ls;  // host copy of d_ls, made by dmwf_legendre_work
     // ring FFT tables (see ring.hip)
     int* d_ring_M = nullptr;           // per q: FFT length (n, or the Bluestein length)
     int* d_ring_blue = nullptr;        // per q: 1 if the ring length is not a power of two

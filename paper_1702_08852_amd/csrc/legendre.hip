@@ -25,6 +25,7 @@
 // (only the contraction FMAs are per map), so the synthesis sum over l needs
 // no communication; the analysis sum over rings is reduced across lanes
 // through LDS once per block of 16 l.  K and MB are per-plan tiles.
+#include <algorithm>
 #include <climits>
 
 #include "legendre_dev.h"
@@ -616,3 +617,61 @@ dmwf_status launch_leg_ana(dmwf_plan* p, const double2* spec, double2* part, con
 }
 
 }  // namespace dmwf
+
+extern "C" dmwf_status dmwf_legendre_work(dmwf_plan* p, int ell, long long* out) {
+    using namespace dmwf;
+    if (!p || !out || ell < 0 || ell > p->lmax) {
+        set_error("legendre_work: NULL argument or ell outside 0..lmax");
+        return DMWF_ERR_INVALID_ARG;
+    }
+    const int nq = p->nq, L = p->lmax;
+    if (p->h_ls.empty()) {
+        p->h_ls.resize((size_t)(L + 1) * nq);
+        DMWF_HIP(hipMemcpy(p->h_ls.data(), p->d_ls, p->h_ls.size() * sizeof(int),
+                           hipMemcpyDeviceToHost));
+    }
+    const int* ls = p->h_ls.data();
+    long long full = (long long)nq * (ell + 1) * (ell + 2) / 2, useful = 0, syn = 0, ana = 0;
+    const int ks = p->syn_k == 1 ? 1 : 2, ka = p->ana_k;
+    for (int m = 0; m <= ell; ++m) {
+        const int* row = ls + (size_t)m * nq;
+        for (int q = 0; q < nq; ++q)
+            if (row[q] <= ell) useful += ell - row[q] + 1;
+        // synthesis: each wave runs its K x 64 ring pairs from the smallest start
+        // in whole 16-l blocks while they fit, then in pairs
+        for (int q0 = 0; q0 < nq; q0 += 64 * ks) {
+            int lo = kNever;
+            for (int q = q0; q < std::min(nq, q0 + 64 * ks); ++q) lo = std::min(lo, row[q]);
+            if (lo > ell) continue;
+            const int span = ell - lo + 1;
+            const int steps = span / kLegB * kLegB + (span % kLegB + 1) / 2 * 2;
+            syn += 64LL * ks * steps;
+        }
+        // analysis: per 16-l block, the slots from the first one holding a
+        // started ring (slot t = ring pairs q0 + 64 t + lane)
+        for (int q0 = 0; q0 < nq; q0 += 64 * ka) {
+            int slo[16];
+            int lo = kNever;
+            for (int t = 0; t < ka; ++t) {
+                slo[t] = kNever;
+                for (int j = 0; j < 64; ++j) {
+                    const int q = q0 + 64 * t + j;
+                    if (q < nq && row[q] <= ell) slo[t] = std::min(slo[t], row[q]);
+                }
+                lo = std::min(lo, slo[t]);
+            }
+            if (lo > ell) continue;
+            for (int l0 = lo; l0 <= ell; l0 += kLegB) {
+                int t0 = ka;
+                for (int t = ka - 1; t >= 0; --t)
+                    if (slo[t] <= l0) t0 = t;
+                ana += 64LL * kLegB * (ka - t0);
+            }
+        }
+    }
+    out[0] = full;
+    out[1] = useful;
+    out[2] = syn;
+    out[3] = ana;
+    return DMWF_OK;
+}

@@ -62,8 +62,11 @@ template <int K, int MB, int P>
 __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn_mx(SynArgs a) {
     constexpr int NP = (MB + 1) / 2;  // map pairs: four MFMA columns each
     __shared__ double2 stage[K][64][kLegWaves][2];
-    // per wave, two chunks: coefficient of (l, column j, pair p) as FP32
+    // per wave, two chunks: coefficient of (l, column j, pair p) as FP32, and
+    // the recurrence multipliers A_l of the chunk (read back as broadcasts, so
+    // the loop waits on LDS only, never on scalar loads)
     __shared__ float coef[kLegWaves][2][kSynCL][4][NP];
+    __shared__ __align__(16) double coefA[kLegWaves][2][kSynCL + 8];
     const int mg = blockIdx.y * MB;
     int ellm[MB];
     const int ell = group_ells<MB>(mg, a.nm, a.ell, a.ell_stride, a.ctrl, a.sel, ellm);
@@ -110,11 +113,17 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn_mx(SynArgs a) {
         const long long base = alm_base(m, a.lmax);
         const double* A = a.A + base;
         float (*cf)[kSynCL][4][NP] = coef[w];
+        double (*cA)[kSynCL + 8] = coefA[w];
         // the next chunk's coefficients in registers while the current one is
         // consumed: entry e = (map e / kSynCL, l e % kSynCL), zero beyond l_iter
         constexpr int FE = (kSynCL * MB + 63) / 64;
         double2 nv[FE];
+        double na = 0.0;  // A_l of the next chunk, l = c + lane (lanes < kSynCL + 8)
         auto fetch = [&](int c) {
+            // whole 16-l blocks run past l_iter (their coefficients are zero):
+            // the multipliers are read up to the block end, inside the table's
+            // padding
+            na = lane < kSynCL + 8 && c + lane <= ell + kLegB ? A[c + lane] : 0.0;
 #pragma unroll
             for (int u = 0; u < FE; ++u) {
                 const int e = lane + 64 * u;
@@ -125,6 +134,7 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn_mx(SynArgs a) {
             }
         };
         auto put = [&](int b) {
+            if (lane < kSynCL + 8) cA[b][lane] = na;
 #pragma unroll
             for (int u = 0; u < FE; ++u) {
                 const int e = lane + 64 * u;
@@ -153,7 +163,8 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn_mx(SynArgs a) {
 #pragma unroll
                     for (int jj = 0; jj < kLegB / 2; ++jj) {
                         const int l = l0 + 2 * jj;
-                        const double Ae = A[l], Ao = A[l + 1];
+                        const double2 AA = *reinterpret_cast<const double2*>(&cA[cur][l - cb]);
+                        const double Ae = AA.x, Ao = AA.y;
                         float be[NP], bo[NP];
 #pragma unroll
                         for (int p = 0; p < NP; ++p) {
@@ -183,7 +194,7 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_syn_mx(SynArgs a) {
                     for (int g = 0; g < 2; ++g) {
                         const int lg = l0 + 8 * g;
                         if (lg > ell) break;
-                        const double* Ag = A + lg;
+                        const double* Ag = &cA[cur][lg - cb];
                         bf4 bhe[NP], ble[NP], bho[NP], blo[NP];
 #pragma unroll
                         for (int p = 0; p < NP; ++p) {

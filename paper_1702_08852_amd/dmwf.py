@@ -77,6 +77,7 @@ def load() -> ctypes.CDLL:
     P = ctypes.POINTER
     lib.dmwf_solve_plans.argtypes = [ci, P(vp), P(vp), P(vp), P(vp), P(_Schedule), P(vp), P(vp),
                                      P(P(_Stats)), P(vp), P(sz), vp]
+    lib.dmwf_legendre_work.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_longlong)]
     lib.dmwf_autotune.argtypes = [vp, vp, sz, vp, ctypes.POINTER(ci), ctypes.POINTER(ctypes.c_float)]
     lib.dmwf_set_tiles.argtypes = [vp, ci, ci, ci, ci]
     lib.dmwf_set_pipeline.argtypes = [vp, ci]
@@ -249,6 +250,14 @@ class Plan:
         times.update({f"ana{4 if t < 2 else 8}x{1 + (t & 1)}": float(ms[8 + t])
                       for t in range(4) if ms[8 + t] >= 0.0})
         return (int(ch[0]), int(ch[1]), int(ch[2]), int(ch[3])), times
+
+    def legendre_work(self, ell: int) -> dict:
+        """dmwf_legendre_work: full, started and issued triples of one FP64
+        Legendre launch at band limit ell."""
+        out = (ctypes.c_longlong * 4)()
+        _check(load().dmwf_legendre_work(self._h, int(ell), out), "dmwf_legendre_work")
+        return {"full": out[0], "started": out[1], "synthesis_issued": out[2],
+                "analysis_issued": out[3]}
 
     def set_tiles(self, syn_k: int, syn_mb: int, ana_k: int, ana_mb: int = 1) -> None:
         _check(load().dmwf_set_tiles(self._h, int(syn_k), int(syn_mb), int(ana_k), int(ana_mb)),
