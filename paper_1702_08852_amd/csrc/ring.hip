@@ -9,13 +9,16 @@
 //              H_k = sum_{m = k mod n} F_m e^{i m phi0}   (aliasing fold, F_{-m} = conj F_m)
 //   analysis   G_m = e^{-i m phi0} R_{m mod n},  R_k = sum_j r_j w^{-jk},  w = e^{2 pi i/n}.
 //
-// The length-n DFTs run in LDS (padded against bank conflicts) as Stockham
-// passes of radix 16 with twiddles computed in registers, and one pass of a
-// smaller radix for the remaining bits; each radix-R butterfly is an
-// in-register radix-2 DFT of R points.  Ring lengths that are not powers of two (polar rings, n = 4i) use
-// Bluestein's chirp-z identity jk = (j^2 + k^2 - (k-j)^2)/2, which turns the
-// DFT into a cyclic convolution of length M >= 2n-1 (a power of two) with the
-// chirp c_t = e^{i pi t^2/n}; the spectrum of the chirp filter is a plan table.
+// The length-n DFTs are Stockham FFTs whose data stay in registers: each
+// thread holds E = 8 elements (stride M / 8) and computes one radix-8
+// butterfly per pass with twiddles formed in registers; between passes the
+// outputs go through LDS (padded against bank conflicts), and a last pass of
+// radix 4 or 2 takes the remaining bits.  Ring lengths that are not powers of
+// two (polar rings, n = 4i), and rings shorter than 16 pixels, use Bluestein's
+// chirp-z identity jk = (j^2 + k^2 - (k-j)^2)/2, which turns the DFT into a
+// cyclic convolution of length M >= 2n-1 (a power of two, at least 16) with
+// the chirp c_t = e^{i pi t^2/n}; the spectrum of the chirp filter is a plan
+// table.
 //
 // In RING_ITER mode the workgroup also performs the pixel step of the paper's
 // Algorithm 2 in residual form: it reads s_prev, writes s, accumulates the
@@ -112,7 +115,8 @@ __device__ __forceinline__ void dit_butterflies(double2 (&v)[R]) {
             constexpr int idx = K * (8 / H);  // e^{-i pi K / H}
             const double2 x1 = v[B + K];
             double2 x2 = v[B + K + H];
-            if constexpr (K != 0) x2 = cmul(make_double2(kC8[idx], -kS8[idx]), x2);
+            if constexpr (idx == 4) x2 = make_double2(x2.y, -x2.x);  // times -i
+            else if constexpr (idx != 0) x2 = cmul(make_double2(kC8[idx], -kS8[idx]), x2);
             v[B + K] = cadd(x1, x2);
             v[B + K + H] = csub(x1, x2);
             dit_butterflies<R, H, B, K + 1>(v);
@@ -137,104 +141,115 @@ __device__ __forceinline__ void dft_small(double2 (&v)[R]) {
     dit_stages<R, 1>(v);
 }
 
-// One Stockham pass of radix R at stride Ns: butterfly j reads elements
-// j + r M/R, twiddles them by e^{-2 pi i (j mod Ns) r / (Ns R)}, transforms,
-// and writes (j / Ns) Ns R + (j mod Ns) + t Ns.  Each thread holds BPT
-// butterflies (j = tid + i nt) in registers between the read and the write,
-// which makes the pass safe in place; requires M / R <= BPT nt.
-template <int R, int BPT>
-__device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int M, int Ns, int tid,
-                                              int nt, const double2* __restrict__ tw) {
-    const int nb = M / R;
-    const int stride = M / R;
-    double2 v[BPT][R];
+// ---------------------------------------------------------------------------
+// FFT on the owner layout.  For a transform of length M (every ring FFT has
+// M >= 16: rings shorter than 16 pixels go through Bluestein at M = 16) with
+// E elements per thread (E = 16 or 8), thread t < S = M / E holds elements
+// t + e S, e = 0..E-1, in x[e].  A Stockham pass of radix R at stride Ns lets
+// butterfly j read elements j + r M / R and write output t to
+// (j / Ns) Ns R + (j mod Ns) + t Ns.  In the owner layout a thread's
+// butterflies j = t + i S (i < E / R) read exactly its own elements, so each
+// pass starts from registers; the outputs go through LDS to the next pass,
+// except after the last pass, whose outputs land on the owner layout again.
+// A transform therefore stores and loads LDS once per pass boundary, and
+// whatever runs before and after it (the fold, the filter product, the pixel
+// step) works on registers.
+// ---------------------------------------------------------------------------
+
+// Radix-R butterflies of one pass at stride Ns on the owner registers: the
+// thread's butterfly i (j = tid + i S) takes x[i + r B] as input r and leaves
+// its output t in x[i + t B], B = E / R.  Radix E has one butterfly per
+// thread; a smaller radix is only ever the last pass (Ns R = M).  TW: the
+// pass has twiddles (every pass but the first, Ns > 1).
+template <int E, int R, bool TW>
+__device__ __forceinline__ void pass_regs(double2 (&x)[E], int M, int Ns, int tid, int S,
+                                          const double2* __restrict__ tw) {
+    constexpr int B = E / R;
+    // Twiddle base of the thread's first butterfly, w = e^{-2 pi i k / (Ns R)}
+    // = omega_M^t with k = j mod Ns, from the two-level root table.  In the
+    // last pass t = j, so butterfly i's base is this one times
+    // omega_M^{i S} = e^{-2 pi i i / E}.
+    double2 base = make_double2(1.0, 0.0);
+    if constexpr (TW) {
+        const int t = R == E ? (tid & (Ns - 1)) * (M / (Ns * E)) : tid;
+        base = cmul(tw[t & 63], tw[64 + (t >> 6)]);
+    }
 #pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-        const int j = tid + i * nt;
-        if (j < nb) {
-            const int k = j & (Ns - 1);
+    for (int i = 0; i < B; ++i) {
+        double2 v[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = buf[pad(j + r * stride)];
-            if (Ns > 1) {
-                // w^r, w = e^{-2 pi i k / (Ns R)} = omega_M^t: the base from the
-                // two-level root table, powers by a product tree of depth at
-                // most four (a few ulps)
-                const int t = k * (M / (Ns * R));
-                double2 wp[4];  // w^1, w^2, w^4, w^8
-                wp[0] = cmul(tw[t & 63], tw[64 + (t >> 6)]);
+        for (int r = 0; r < R; ++r) v[r] = x[i + r * B];
+        if constexpr (TW) {
+            // powers w^r one product at a time (at most R - 1 roundings)
+            const int ci = i * (16 / E);  // e^{-2 pi i i / E} = e^{-i pi ci / 8}
+            const double2 w1 = i == 0 ? base : cmul(base, make_double2(kC8[ci], -kS8[ci]));
+            double2 w = w1;
 #pragma unroll
-                for (int b = 1; b < 4; ++b) wp[b] = cmul(wp[b - 1], wp[b - 1]);
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    // w^r from the binary digits of r, used at once
-                    double2 t = wp[ilog2(r & -r)];
-#pragma unroll
-                    for (int b = ilog2(r & -r) + 1; b < 4; ++b)
-                        if (r & (1 << b)) t = cmul(t, wp[b]);
-                    v[i][r] = cmul(t, v[i][r]);
-                }
+            for (int r = 1; r < R; ++r) {
+                v[r] = cmul(w, v[r]);
+                if (r + 1 < R) w = cmul(w, w1);
             }
-            dft_small<R>(v[i]);
         }
+        dft_small<R>(v);
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[i + r * B] = v[r];
+    }
+}
+
+// Outputs of a radix-E pass at stride Ns to LDS in Stockham order, then the
+// owner layout back for the next pass.
+template <int E>
+__device__ __forceinline__ void exchange(double2 (&x)[E], double2* buf, int Ns, int tid, int S,
+                                         bool act) {
+    if (act) {
+        const int o = (tid & ~(Ns - 1)) * E + (tid & (Ns - 1));
+#pragma unroll
+        for (int t = 0; t < E; ++t) buf[pad(o + t * Ns)] = x[t];
     }
     lds_barrier();
+    if (act) {
 #pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-        const int j = tid + i * nt;
-        if (j < nb) {
-            const int k = j & (Ns - 1);
-            const int o = (j / Ns) * Ns * R + k;
-#pragma unroll
-            for (int t = 0; t < R; ++t) buf[pad(o + t * Ns)] = v[i][t];
-        }
+        for (int e = 0; e < E; ++e) x[e] = buf[pad(tid + e * S)];
     }
     lds_barrier();
 }
 
-// Forward DFT of length M = 2^logM in place, natural order in and out:
-// radix-16 passes while four or more bits remain, then one pass of radix 8,
-// 4 or 2.  MFIX > 0 fixes M at compile time (one code path per launch
-// class), MFIX = 0 takes it at run time.  Radix-16 passes keep one butterfly
-// per thread, which needs M / 16 <= NT.
-template <int NT, int MFIX>
-__device__ __forceinline__ void fft(double2* buf, int M, int logM, int tid,
-                                    const double2* __restrict__ tw) {
-    static_assert(MFIX == 0 || MFIX / 16 <= NT, "one radix-16 butterfly per thread");
+// Forward DFT of length M = 2^logM on the owner layout: radix-E passes
+// while log2 E or more bits remain, then one pass of the remaining radix.
+// MFIX > 0 fixes M at compile time (one code path per launch class), MFIX = 0
+// takes it at run time.  Every thread of the workgroup calls it (it holds
+// barriers).
+template <int E, int MFIX>
+__device__ __forceinline__ void fft_owner(double2 (&x)[E], double2* buf, int M, int logM, int tid,
+                                          const double2* __restrict__ tw) {
+    constexpr int LE = ilog2(E);
     // opaque copy of the thread index: keeps the passes' LDS addresses from
     // being hoisted out of the caller's loop into long-lived registers
     asm volatile("" : "+v"(tid));
     const int lm = MFIX > 0 ? ilog2(MFIX) : logM;
-    int Ns = 1;
+    const int S = M / E;
+    const bool act = tid < S;
+    const int nmain = lm / LE;
+    const int L = lm - nmain * LE;
+    // first pass (radix E, no twiddles), then radix-E passes at Ns = E, E^2,
+    // ..., then the last pass of radix 2^L when L > 0
+    if (act) pass_regs<E, E, false>(x, M, 1, tid, S, tw);
+    if (nmain > 1 || L != 0) exchange<E>(x, buf, 1, tid, S, act);
+    int Ns = E;
 #pragma unroll 1
-    for (int p = 0; p < (lm >> 2); ++p) {
-        stockham_pass<16, 1>(buf, M, Ns, tid, NT, tw);
-        Ns <<= 4;
+    for (int p = 1; p < nmain; ++p) {
+        if (act) pass_regs<E, E, true>(x, M, Ns, tid, S, tw);
+        if (p < nmain - 1 || L != 0) exchange<E>(x, buf, Ns, tid, S, act);
+        Ns *= E;
     }
-    if constexpr (MFIX > 0) {
-        constexpr int L = ilog2(MFIX) & 3;
-        constexpr int NB = MFIX >> L;
-        constexpr int BPT = NB > NT ? NB / NT : 1;
-        if constexpr (L == 3) stockham_pass<8, BPT>(buf, M, Ns, tid, NT, tw);
-        else if constexpr (L == 2) stockham_pass<4, BPT>(buf, M, Ns, tid, NT, tw);
-        else if constexpr (L == 1) stockham_pass<2, BPT>(buf, M, Ns, tid, NT, tw);
-    } else {
-        const int left = lm & 3;
-        if (left > 0) {
-            const int nb = M >> left;
-            const int bpt = nb > NT ? nb / NT : 1;
-            if (left == 3) {
-                if (bpt == 1) stockham_pass<8, 1>(buf, M, Ns, tid, NT, tw);
-                else stockham_pass<8, 2>(buf, M, Ns, tid, NT, tw);
-            } else if (left == 2) {
-                if (bpt == 1) stockham_pass<4, 1>(buf, M, Ns, tid, NT, tw);
-                else if (bpt == 2) stockham_pass<4, 2>(buf, M, Ns, tid, NT, tw);
-                else stockham_pass<4, 4>(buf, M, Ns, tid, NT, tw);
-            } else {
-                if (bpt == 1) stockham_pass<2, 1>(buf, M, Ns, tid, NT, tw);
-                else if (bpt == 2) stockham_pass<2, 2>(buf, M, Ns, tid, NT, tw);
-                else if (bpt == 4) stockham_pass<2, 4>(buf, M, Ns, tid, NT, tw);
-                else stockham_pass<2, 8>(buf, M, Ns, tid, NT, tw);
-            }
+    if (act) {
+        if constexpr (E == 16) {
+            if (L == 3) pass_regs<E, 8, true>(x, M, Ns, tid, S, tw);
+            else if (L == 2) pass_regs<E, 4, true>(x, M, Ns, tid, S, tw);
+            else if (L == 1) pass_regs<E, 2, true>(x, M, Ns, tid, S, tw);
+        } else {
+            if (L == 2) pass_regs<E, 4, true>(x, M, Ns, tid, S, tw);
+            else if (L == 1) pass_regs<E, 2, true>(x, M, Ns, tid, S, tw);
         }
     }
 }
@@ -252,29 +267,23 @@ __device__ __forceinline__ void root_table(double2* tw, int M, int tid) {
     }
 }
 
-// Middle step of Bluestein's algorithm: buf = FFT_M(a) on entry; leaves
-// conj(buf B) / M, whose forward FFT is conj(M conv), conv = a (*) b the
-// cyclic convolution of length M (B = FFT_M(b) from the plan).
-template <int NT>
-__device__ __forceinline__ void filter_product(double2* buf, int M, const double2* __restrict__ B,
-                                               int tid) {
+// Middle step of Bluestein's algorithm on the owner layout: x = FFT_M(a) on
+// entry; leaves conj(x B) / M, whose forward FFT is conj(M conv), conv = a (*) b
+// the cyclic convolution of length M (B = FFT_M(b) from the plan, loaded into
+// the owner layout by load_owner before the FFT that precedes this step).
+template <int E>
+__device__ __forceinline__ void load_owner(double2 (&v)[E], const double2* __restrict__ src,
+                                           int tid, int S) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = src[tid + e * S];
+}
+template <int E>
+__device__ __forceinline__ void filter_regs(double2 (&x)[E], int M, const double2 (&b)[E]) {
     const double inv = 1.0 / M;
-    // eight filter values in flight per thread before they are used
-    for (int k0 = tid; k0 < M; k0 += 8 * NT) {
-        double2 b[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int k = k0 + u * NT;
-            b[u] = k < M ? B[k] : make_double2(0.0, 0.0);
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int k = k0 + u * NT;
-            if (k < M) {
-                const double2 ak = cmul(buf[pad(k)], b[u]);
-                buf[pad(k)] = make_double2(ak.x * inv, -ak.y * inv);
-            }
-        }
+    for (int e = 0; e < E; ++e) {
+        const double2 v = cmul(x[e], b[e]);
+        x[e] = make_double2(v.x * inv, -v.y * inv);
     }
 }
 
@@ -297,25 +306,57 @@ __device__ __forceinline__ double2 block_sum2(double u, double v, double2* scrat
     return t;
 }
 
-// Analysis input z_j = r^N_j + i r^S_j [times conj(c_j) for Bluestein rings],
-// zero-padded to M.
-template <int NT, int J>
-__device__ __forceinline__ void ana_input(double2* buf, const double (&rn)[J],
-                                          const double (&rs)[J], int n, int M, bool blue,
-                                          const double2* __restrict__ ch, int tid) {
-#pragma unroll
-    for (int t = 0; t < J; ++t) {
-        const int j = tid + t * NT;
-        if (j < n) {
-            double2 z = make_double2(rn[t], rs[t]);
-            if (blue) z = cmul(z, conj2(ch[j]));
-            buf[pad(j)] = z;
-        }
+// Contribution of mode m of the F row to the DFT input Z = H^N + i H^S:
+// +m feeds bin kp with zp, -m feeds bin km with zm (F_{-m} = conj F_m).
+struct FoldTerm {
+    double2 zp, zm;
+    int kp, km;
+};
+
+__device__ __forceinline__ FoldTerm fold_term(double2 fn, double2 fs, int m, int n, double c,
+                                              bool eq) {
+    double sn, cs;
+    sincospi(m * c, &sn, &cs);
+    const double2 ph = make_double2(cs, sn);
+    if (m == 0) {
+        fn.y = 0.0;
+        fs.y = 0.0;
     }
-    for (int j = n + tid; j < M; j += NT) buf[pad(j)] = make_double2(0.0, 0.0);
+    if (eq) fs = make_double2(0.0, 0.0);
+    const double2 en = cmul(fn, ph), es = cmul(fs, ph);
+    FoldTerm f;
+    f.zp = make_double2(en.x - es.y, en.y + es.x);
+    f.zm = make_double2(en.x + es.y, es.x - en.y);
+    f.kp = m % n;
+    f.km = f.kp == 0 ? 0 : n - f.kp;
+    return f;
 }
 
-template <int NT, int J, int MFIX>
+// Bin m of the analysed ring pair, G^N_m and G^S_m, from Z_k and Z_{n-k}
+// (k = m mod n), both already divided by the chirp for Bluestein rings.
+__device__ __forceinline__ void unfold_store(double2 zk, double2 zc, int m, double c, bool eq,
+                                             double2* g) {
+    const double2 czc = conj2(zc);
+    const double2 rN = make_double2(0.5 * (zk.x + czc.x), 0.5 * (zk.y + czc.y));
+    const double2 dS = csub(zk, czc);  // R^S = -i dS / 2
+    const double2 rS = make_double2(0.5 * dS.y, -0.5 * dS.x);
+    double sn, cs;
+    sincospi(m * c, &sn, &cs);
+    const double2 ph = make_double2(cs, -sn);
+    double2 gN = cmul(rN, ph), gS = eq ? make_double2(0.0, 0.0) : cmul(rS, ph);
+    if (m == 0) {
+        gN.y = 0.0;
+        gS.y = 0.0;
+    }
+    g[0] = gN;
+    g[1] = gS;
+}
+
+// One workgroup per ring pair.  NT threads, E FFT elements per thread in the
+// owner layout, J of them pixels (n <= J S), MFIX the FFT length of the class
+// (0: run time).  PREF (J <= 4): the pixel data are loaded before the last
+// synthesis FFT.
+template <int NT, int E, int J, int MFIX>
 __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     extern __shared__ double2 buf[];
     __shared__ double2 red[NT / 64];
@@ -333,7 +374,7 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     double2* spec = a.spec + map * a.spec_map;
     const int q = a.qlist[blockIdx.x];
     const int n = a.g.nph[q];
-    const int M = a.Mq[q];
+    const int M = MFIX > 0 ? MFIX : a.Mq[q];
     const int logM = 31 - __clz(M);
     const bool blue = a.blue[q] != 0;
     const double2* ch = a.chirp + a.coff[q];
@@ -359,158 +400,152 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     const double xi_ = ctrl ? ctrl->xi : a.io.xi;
     const double alpha_ = ctrl ? ctrl->alpha : a.io.alpha;
     const int tid = threadIdx.x;
-    // m per thread and batch in the fold and unfold
-    constexpr int FB = NT >= 512 ? 5 : 6;
+    // owner layout: stride S, E elements per thread, threads tid < S active
+    const int S = M / E;
+    const bool act = tid < S;
+    // modes per thread and batch in the fold
+    constexpr int FB = NT >= 512 ? 4 : 6;
+    constexpr bool PREF = J <= 4;
 
+    double2 x[E];
     const bool syn = (a.mode == RING_SYN || a.mode == RING_ITER || a.mode == RING_SYN_WRES);
-    root_table<NT>(tw, M, tid);  // read after the barrier that ends the input stage
+    // Chirp of a Bluestein ring at the thread's elements (k < n <= J S): with
+    // PREF held in registers for its four uses (fold input, pixel output,
+    // pixel input, analysis output), else loaded at each use.
+    double2 chr[PREF ? J : 1];
+    if constexpr (PREF) {
+#pragma unroll
+        for (int e = 0; e < J; ++e) {
+            const int k = tid + e * S;
+            chr[e] = blue && act && k < n ? ch[k] : make_double2(1.0, 0.0);
+        }
+    }
+    auto chirp = [&](int e) -> double2 {
+        if constexpr (PREF) return chr[e < J ? e : 0];
+        else return ch[tid + e * S];
+    };
+    root_table<NT>(tw, M, tid);  // read after the barriers of the input stage
     if (syn) {
         // Fold F into the DFT input x_k = conj(Z_k) [times conj(c_k)],
-        // Z_k = H^N_k + i H^S_k, H_k = sum over m = k mod n of F_m e^{i m phi0}
-        // with F_{-m} = conj(F_m).  The row of F is read once, coalesced, and
-        // scattered: m feeds bin m mod n, and -m feeds bin -m mod n.
+        // Z_k = H^N_k + i H^S_k, H_k = sum over m = k mod n of F_m e^{i m phi0}.
+        // The row of F is read once, coalesced, and scattered to the bins in
+        // LDS: m feeds bin m mod n, and -m feeds bin -m mod n.  Bins collide
+        // when 2 ell > n (summed with LDS atomics on zeroed bins); at
+        // 2 ell = n only m = n/2 meets -m, which one thread handles alone.
         const double2* Fq = spec + (size_t)q * a.lp * 2;
-        // Bins collide when 2 ell > n; at 2 ell = n only m = n/2 meets -m,
-        // which one thread handles alone.
         const bool alias = 2 * ell > n;
         if (alias) {
-            for (int k = tid; k < M; k += NT) buf[pad(k)] = make_double2(0.0, 0.0);
+            for (int k = tid; k < n; k += NT) buf[pad(k)] = make_double2(0.0, 0.0);
             lds_barrier();
-        } else {
-            for (int k = tid; k < M; k += NT)
-                if (k >= n || (k > ell && k < n - ell)) buf[pad(k)] = make_double2(0.0, 0.0);
         }
         for (int m0 = tid; m0 <= ell; m0 += FB * NT) {
-            // loads for FB m first (F row entries and the chirp at their bins):
-            // at lmax = 2 nside one batch covers the row, so the fold waits on
-            // memory once
-            double2 fnv[FB], fsv[FB], cpv[FB], cmv[FB];
+            // loads for FB modes first: at lmax = 2 nside one batch covers
+            // the row, so the fold waits on memory once
+            double2 fnv[FB], fsv[FB];
 #pragma unroll
             for (int u = 0; u < FB; ++u) {
                 const int m = m0 + u * NT;
-                fnv[u] = fsv[u] = cpv[u] = cmv[u] = make_double2(0.0, 0.0);
+                fnv[u] = fsv[u] = make_double2(0.0, 0.0);
                 if (m <= ell) {
                     fnv[u] = Fq[2 * m];
                     fsv[u] = Fq[2 * m + 1];
-                    if (blue && !alias) {
-                        const int kp = m % n;
-                        cpv[u] = ch[kp];
-                        cmv[u] = ch[kp == 0 ? 0 : n - kp];
-                    }
                 }
             }
 #pragma unroll
             for (int u = 0; u < FB; ++u) {
                 const int m = m0 + u * NT;
                 if (m > ell) continue;
-                double sn, cs;
-                sincospi(m * c, &sn, &cs);
-                const double2 ph = make_double2(cs, sn);
-                double2 fn = fnv[u], fs = fsv[u];
-                if (m == 0) {
-                    fn.y = 0.0;
-                    fs.y = 0.0;
-                }
-                if (eq) fs = make_double2(0.0, 0.0);
-                const double2 en = cmul(fn, ph), es = cmul(fs, ph);
-                // contribution of +m: en + i es; of -m: conj(en) + i conj(es)
-                const double2 zp = make_double2(en.x - es.y, en.y + es.x);
-                const double2 zm = make_double2(en.x + es.y, es.x - en.y);
-                const int kp = m % n;
-                const int km = kp == 0 ? 0 : n - kp;
+                const FoldTerm f = fold_term(fnv[u], fsv[u], m, n, c, eq);
                 if (alias) {
-                    atomicAdd(&buf[pad(kp)].x, zp.x);
-                    atomicAdd(&buf[pad(kp)].y, zp.y);
+                    atomicAdd(&buf[pad(f.kp)].x, f.zp.x);
+                    atomicAdd(&buf[pad(f.kp)].y, f.zp.y);
                     if (m > 0) {
-                        atomicAdd(&buf[pad(km)].x, zm.x);
-                        atomicAdd(&buf[pad(km)].y, zm.y);
+                        atomicAdd(&buf[pad(f.km)].x, f.zm.x);
+                        atomicAdd(&buf[pad(f.km)].y, f.zm.y);
                     }
+                } else if (m > 0 && f.km == f.kp) {
+                    buf[pad(f.kp)] = cadd(f.zp, f.zm);
                 } else {
-                    double2 v = conj2(zp);
-                    if (blue) v = cmul(v, conj2(cpv[u]));
-                    if (m > 0) {
-                        double2 w2 = conj2(zm);
-                        if (blue) w2 = cmul(w2, conj2(cmv[u]));
-                        if (km == kp) v = cadd(v, w2);
-                        else buf[pad(km)] = w2;
-                    }
-                    buf[pad(kp)] = v;
+                    buf[pad(f.kp)] = f.zp;
+                    if (m > 0) buf[pad(f.km)] = f.zm;
                 }
             }
         }
         lds_barrier();
-        if (alias) {
-            for (int k = tid; k < n; k += NT) {
-                double2 v = conj2(buf[pad(k)]);
-                if (blue) v = cmul(v, conj2(ch[k]));
-                buf[pad(k)] = v;
-            }
-            lds_barrier();
-        }
-    } else {
-        // analysis only: the input comes from the pixels
-        double rn[J], rs[J];
+        // owner layout: conj, and the chirp of Bluestein rings; bins no mode
+        // reached (n <= k, or ell < k < n - ell without aliasing) are zero
 #pragma unroll
-        for (int t = 0; t < J; ++t) {
-            const int j = tid + t * NT;
-            rn[t] = 0.0;
-            rs[t] = 0.0;
-            if (j >= n) continue;
-            for (int h = 0; h < (eq ? 1 : 2); ++h) {
-                const long long p = (h == 0 ? st0 : st1) + j;
-                double v;
-                switch (a.pix) {
-                    case PIX_FIRST: v = ww[p] > 0.0 ? dd[p] : 0.0; break;
-                    case PIX_WRES: v = ww[p] * (dd[p] - min_[p]); break;
-                    case PIX_WD: v = ww[p] * dd[p]; break;
-                    case PIX_CRES: {
-                        const double w = ww[p];
-                        const double cc = xi_ * w / fma(xi_ - alpha_, w, 1.0);
-                        v = cc * (dd[p] - min_[p]);
-                        break;
-                    }
-                    default: v = min_[p]; break;
-                }
-                if (h == 0) rn[t] = v;
-                else rs[t] = v;
+        for (int e = 0; e < E; ++e) {
+            const int k = tid + e * S;
+            double2 v = make_double2(0.0, 0.0);
+            if (act && k < n && (alias || k <= ell || k >= n - ell)) {
+                v = conj2(buf[pad(k)]);
+                if (blue && e < J) v = cmul(v, conj2(chirp(e)));
             }
+            x[e] = v;
         }
-        ana_input<NT, J>(buf, rn, rs, n, M, blue, ch, tid);
-    }
-    lds_barrier();
+        lds_barrier();
 
-    // Each DFT is one FFT, or two around the filter product for Bluestein
-    // rings, written as a loop so that the FFT code appears once per direction
-    // (the kernel's instruction footprint stays within the instruction cache).
-    if (syn) {
-#pragma unroll 1
-        for (int step = 0; step < (blue ? 2 : 1); ++step) {
-            fft<NT, MFIX>(buf, M, logM, tid, tw);
-            if (blue && step == 0) {
-                filter_product<NT>(buf, M, B, tid);
-                lds_barrier();
+        // Each DFT is one FFT, or two around the filter product for Bluestein
+        // rings.  Memory that a later step needs is loaded before the FFT
+        // that precedes it, so that its latency hides behind the FFT: the
+        // filter spectrum, and (PREF: few pixel elements per thread) the
+        // pixel data of the pixel step.
+        double pd[PREF ? 4 * J : 1];
+        if (blue) {
+            double2 bq[E];
+            if (act) load_owner<E>(bq, B, tid, S);
+            fft_owner<E, MFIX>(x, buf, M, logM, tid, tw);
+            if (act) filter_regs<E>(x, M, bq);
+        }
+        if constexpr (PREF) {
+#pragma unroll
+            for (int e = 0; e < J; ++e) {
+                const int j = tid + e * S;
+                double* v = pd + 4 * e;
+                v[0] = v[1] = v[2] = v[3] = 0.0;
+                if (act && j < n && a.mode != RING_SYN) {
+                    v[0] = dd[st0 + j];
+                    v[1] = ww[st0 + j];
+                    if (!eq) {
+                        v[2] = dd[st1 + j];
+                        v[3] = ww[st1 + j];
+                    }
+                }
             }
         }
-        // y_j = IDFT(Z)_j: blue: c_j buf_j; else conj(buf_j).  s^N = Re y, s^S = Im y.
-        // Pixel data are loaded for JH of the thread's pixels first, then
+        fft_owner<E, MFIX>(x, buf, M, logM, tid, tw);
+        // y_j = IDFT(Z)_j: blue: c_j x_j; else conj(x_j).  s^N = Re y, s^S = Im y.
+        // Pixel data are loaded for JH of the thread's elements first, then
         // combined and stored, so the loads of one pixel never wait on the
-        // store of another.  The residual r goes straight back into the slot
-        // of y as the analysis input z_j = r^N_j + i r^S_j [times conj(c_j)]:
-        // each slot is read and written by the same thread only.
+        // store of another.  The residual r replaces y in the register as
+        // the analysis input z_j = r^N_j + i r^S_j [times conj(c_j)], and
+        // zero beyond n (the padding of Bluestein rings).
         double num = 0.0, den = 0.0;
-        constexpr int JH = J < 4 ? J : 4;
+        constexpr int JH = 4;
 #pragma unroll
-        for (int t0 = 0; t0 < J; t0 += JH) {
+        for (int e0 = 0; e0 < E; e0 += JH) {
             double yN[JH], yS[JH], dN[JH], dS[JH], wN[JH], wS[JH], pN[JH], pS[JH];
 #pragma unroll
             for (int u = 0; u < JH; ++u) {
-                const int j = tid + (t0 + u) * NT;
+                const int e = e0 + u;
+                const int j = tid + e * S;
                 yN[u] = yS[u] = dN[u] = dS[u] = wN[u] = wS[u] = pN[u] = pS[u] = 0.0;
-                if (j < n) {
-                    const double2 y = blue ? cmul(ch[j], buf[pad(j)]) : conj2(buf[pad(j)]);
+                if (e < J && act && j < n) {
+                    const double2 y = blue ? cmul(chirp(e), x[e]) : conj2(x[e]);
                     yN[u] = y.x;
                     yS[u] = y.y;
-                    if (a.mode != RING_SYN) {
+                    if constexpr (PREF) {
+                        const double* v = pd + 4 * (e < J ? e : 0);
+                        dN[u] = v[0];
+                        wN[u] = v[1];
+                        dS[u] = v[2];
+                        wS[u] = v[3];
+                        if (a.mode == RING_ITER && !a.io.first) {
+                            pN[u] = smap[st0 + j];
+                            if (!eq) pS[u] = smap[st1 + j];
+                        }
+                    } else if (a.mode != RING_SYN) {
                         dN[u] = dd[st0 + j];
                         wN[u] = ww[st0 + j];
                         if (!eq) {
@@ -526,40 +561,38 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
             }
 #pragma unroll
             for (int u = 0; u < JH; ++u) {
-                const int j = tid + (t0 + u) * NT;
-                if (j >= n) continue;
-                double rn = 0.0, rs = 0.0;
-                if (a.mode == RING_SYN) {
-                    mout[st0 + j] = yN[u];
-                    if (!eq) mout[st1 + j] = yS[u];
-                    continue;
-                } else if (a.mode == RING_SYN_WRES) {
-                    rn = wN[u] * (dN[u] - yN[u]);
-                    rs = eq ? 0.0 : wS[u] * (dS[u] - yS[u]);
-                } else {
-                    const double xi = xi_, xa = xi_ - alpha_;
-                    double ds = yN[u] - pN[u];
-                    num = fma(ds, ds, num);
-                    den = fma(yN[u], yN[u], den);
-                    smap[st0 + j] = yN[u];
-                    rn = xi * wN[u] / fma(xa, wN[u], 1.0) * (dN[u] - yN[u]);
-                    if (!eq) {
-                        ds = yS[u] - pS[u];
+                const int e = e0 + u;
+                const int j = tid + e * S;
+                double2 z = make_double2(0.0, 0.0);
+                if (e < J && act && j < n) {
+                    double rn = 0.0, rs = 0.0;
+                    if (a.mode == RING_SYN) {
+                        mout[st0 + j] = yN[u];
+                        if (!eq) mout[st1 + j] = yS[u];
+                    } else if (a.mode == RING_SYN_WRES) {
+                        rn = wN[u] * (dN[u] - yN[u]);
+                        rs = eq ? 0.0 : wS[u] * (dS[u] - yS[u]);
+                    } else {
+                        const double xi = xi_, xa = xi_ - alpha_;
+                        double ds = yN[u] - pN[u];
                         num = fma(ds, ds, num);
-                        den = fma(yS[u], yS[u], den);
-                        smap[st1 + j] = yS[u];
-                        rs = xi * wS[u] / fma(xa, wS[u], 1.0) * (dS[u] - yS[u]);
+                        den = fma(yN[u], yN[u], den);
+                        smap[st0 + j] = yN[u];
+                        rn = xi * wN[u] / fma(xa, wN[u], 1.0) * (dN[u] - yN[u]);
+                        if (!eq) {
+                            ds = yS[u] - pS[u];
+                            num = fma(ds, ds, num);
+                            den = fma(yS[u], yS[u], den);
+                            smap[st1 + j] = yS[u];
+                            rs = xi * wS[u] / fma(xa, wS[u], 1.0) * (dS[u] - yS[u]);
+                        }
                     }
+                    z = make_double2(rn, rs);
+                    if (blue) z = cmul(z, conj2(chirp(e)));
                 }
-                double2 z = make_double2(rn, rs);
-                if (blue) z = cmul(z, conj2(ch[j]));
-                buf[pad(j)] = z;
+                x[e] = z;
             }
         }
-        // zero padding of the analysis input (Bluestein rings): slots no
-        // thread reads in this stage
-        if (a.mode != RING_SYN)
-            for (int j = n + tid; j < M; j += NT) buf[pad(j)] = make_double2(0.0, 0.0);
         if (a.mode == RING_ITER) {
             // red[] is written once per launch: no barrier needed before it
             const double2 t = block_sum2<NT>(num, den, red);
@@ -570,56 +603,62 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
             }
         }
         if (a.mode == RING_SYN) return;
-        lds_barrier();
-    }
-#pragma unroll 1
-    for (int step = 0; step < (blue ? 2 : 1); ++step) {
-        fft<NT, MFIX>(buf, M, logM, tid, tw);
-        if (blue && step == 0) {
-            filter_product<NT>(buf, M, B, tid);
-            lds_barrier();
-        }
-    }
-    // Z_k = DFT(z)_k; split the two real rings and unfold to m
-    for (int m0 = tid; m0 <= ella; m0 += FB * NT) {
-        double2 ckv[FB], ccv[FB];
+    } else {
+        // analysis only: the input z_j = r^N_j + i r^S_j [times conj(c_j)]
+        // comes from the pixels, zero beyond n
 #pragma unroll
-        for (int u = 0; u < FB; ++u) {
-            const int m = m0 + u * NT;
-            ckv[u] = ccv[u] = make_double2(1.0, 0.0);
-            if (blue && m <= ella) {
-                const int k = m % n;
-                ckv[u] = ch[k];
-                ccv[u] = ch[k == 0 ? 0 : n - k];
-            }
-        }
+        for (int e = 0; e < E; ++e) {
+            const int j = tid + e * S;
+            double2 z = make_double2(0.0, 0.0);
+            if (e < J && act && j < n) {
 #pragma unroll
-        for (int u = 0; u < FB; ++u) {
-            const int m = m0 + u * NT;
-            if (m > ella) continue;
-            const int k = m % n;
-            const int kc = k == 0 ? 0 : n - k;
-            double2 zk = buf[pad(k)], zc = buf[pad(kc)];
-            if (blue) {
-                zk = conj2(cmul(ckv[u], zk));
-                zc = conj2(cmul(ccv[u], zc));
+                for (int h = 0; h < 2; ++h) {
+                    if (h == 1 && eq) break;
+                    const long long p = (h == 0 ? st0 : st1) + j;
+                    double v;
+                    switch (a.pix) {
+                        case PIX_FIRST: v = ww[p] > 0.0 ? dd[p] : 0.0; break;
+                        case PIX_WRES: v = ww[p] * (dd[p] - min_[p]); break;
+                        case PIX_WD: v = ww[p] * dd[p]; break;
+                        case PIX_CRES: {
+                            const double w = ww[p];
+                            const double cc = xi_ * w / fma(xi_ - alpha_, w, 1.0);
+                            v = cc * (dd[p] - min_[p]);
+                            break;
+                        }
+                        default: v = min_[p]; break;
+                    }
+                    if (h == 0) z.x = v;
+                    else z.y = v;
+                }
+                if (blue) z = cmul(z, conj2(chirp(e)));
             }
-            const double2 czc = conj2(zc);
-            const double2 rN = make_double2(0.5 * (zk.x + czc.x), 0.5 * (zk.y + czc.y));
-            const double2 dS = csub(zk, czc);  // R^S = -i dS / 2
-            const double2 rS = make_double2(0.5 * dS.y, -0.5 * dS.x);
-            double sn, cs;
-            sincospi(m * c, &sn, &cs);
-            const double2 ph = make_double2(cs, -sn);
-            double2 gN = cmul(rN, ph), gS = eq ? make_double2(0.0, 0.0) : cmul(rS, ph);
-            if (m == 0) {
-                gN.y = 0.0;
-                gS.y = 0.0;
-            }
-            double2* g = spec + ((size_t)q * a.lp + m) * 2;
-            g[0] = gN;
-            g[1] = gS;
+            x[e] = z;
         }
+        lds_barrier();  // the root table
+    }
+
+    if (blue) {
+        double2 bq[E];
+        if (act) load_owner<E>(bq, B, tid, S);
+        fft_owner<E, MFIX>(x, buf, M, logM, tid, tw);
+        if (act) filter_regs<E>(x, M, bq);
+    }
+    fft_owner<E, MFIX>(x, buf, M, logM, tid, tw);
+    // Z_k = DFT(z)_k [divided by the chirp] to LDS; split the two real rings
+    // and unfold to m
+    if (act) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = tid + e * S;
+            if (k < n) buf[pad(k)] = blue ? conj2(cmul(chirp(e), x[e])) : x[e];
+        }
+    }
+    lds_barrier();
+    for (int m = tid; m <= ella; m += NT) {
+        const int k = m % n;
+        const int kc = k == 0 ? 0 : n - k;
+        unfold_store(buf[pad(k)], buf[pad(kc)], m, c, eq, spec + ((size_t)q * a.lp + m) * 2);
     }
 }
 
@@ -638,46 +677,70 @@ __global__ __launch_bounds__(NT) void k_chirp_spectrum(const int* __restrict__ q
     const int q = qlist[blockIdx.x];
     const int n = nph[q], M = Mq[q];
     const int logM = 31 - __clz(M);
+    const int S = M >> 4;
+    const int tid = threadIdx.x;
     const double2* ch = chirp + coff[q];
-    for (int t = threadIdx.x; t < M; t += NT) {
+    double2 x[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int t = tid + e * S;
         double2 v = make_double2(0.0, 0.0);
-        if (t < n) v = ch[t];
-        else if (M - t < n) v = ch[M - t];
-        buf[pad(t)] = v;
+        if (tid < S) {
+            if (t < n) v = ch[t];
+            else if (M - t < n) v = ch[M - t];
+        }
+        x[e] = v;
     }
-    root_table<NT>(tw, M, threadIdx.x);
+    root_table<NT>(tw, M, tid);
     lds_barrier();
-    fft<NT, 0>(buf, M, logM, threadIdx.x, tw);
-    for (int k = threadIdx.x; k < M; k += NT) bspec[boff[q] + k] = buf[pad(k)];
+    fft_owner<16, 0>(x, buf, M, logM, tid, tw);
+    if (tid < S) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) bspec[boff[q] + tid + e * S] = x[e];
+    }
 }
 
 int ring_class(int M) { return M <= 1024 ? 0 : (M == 2048 ? 1 : (M == 4096 ? 2 : 3)); }
 
-// Threads per class: one radix-16 butterfly per thread and pass at the
-// largest length of the class; the FFT length is fixed at compile time except
-// in the class of short rings.
-void launch_class(int cls, dim3 grid, size_t lds, hipStream_t s, const RingArgs& a) {
-    switch (cls) {
-        case 0: hipLaunchKernelGGL((k_ring_fft<64, 16, 0>), grid, dim3(64), lds, s, a); break;
-        case 1: hipLaunchKernelGGL((k_ring_fft<128, 16, 2048>), grid, dim3(128), lds, s, a); break;
-        case 2: hipLaunchKernelGGL((k_ring_fft<256, 16, 4096>), grid, dim3(256), lds, s, a); break;
-        default: hipLaunchKernelGGL((k_ring_fft<512, 8, 8192>), grid, dim3(512), lds, s, a); break;
-    }
+// Launch shape per class: threads and FFT elements per thread (one radix-E
+// butterfly per thread and pass at the largest length of the class); the FFT
+// length is fixed at compile time except in the class of short rings.  Eight
+// elements per thread (four passes at M = 4096) measured faster than sixteen
+// (three passes): half the registers, so twice the waves per CU.
+constexpr int kClassE[kRingClasses] = {8, 8, 8, 8};
+constexpr int kClassMaxM[kRingClasses] = {1024, 2048, 4096, 8192};
+constexpr int kClassThreads[kRingClasses] = {kClassMaxM[0] / kClassE[0], kClassMaxM[1] / kClassE[1],
+                                             kClassMaxM[2] / kClassE[2], kClassMaxM[3] / kClassE[3]};
+
+template <int C>
+void launch_one(dim3 grid, size_t lds, hipStream_t s, const RingArgs& a) {
+    constexpr int E = kClassE[C], NT = kClassThreads[C];
+    // the Bluestein class has n <= M / 2: half the elements are pixels
+    constexpr int J = C == 3 ? E / 2 : E;
+    constexpr int MF = C == 0 ? 0 : kClassMaxM[C];
+    hipLaunchKernelGGL((k_ring_fft<NT, E, J, MF>), grid, dim3(NT), lds, s, a);
 }
 
-const int kClassMaxM[kRingClasses] = {1024, 2048, 4096, 8192};
+void launch_class(int cls, dim3 grid, size_t lds, hipStream_t s, const RingArgs& a) {
+    switch (cls) {
+        case 0: launch_one<0>(grid, lds, s, a); break;
+        case 1: launch_one<1>(grid, lds, s, a); break;
+        case 2: launch_one<2>(grid, lds, s, a); break;
+        default: launch_one<3>(grid, lds, s, a); break;
+    }
+}
 
 size_t class_lds(int c) { return (size_t)(kClassMaxM[c] + kClassMaxM[c] / 16) * sizeof(double2); }
 
 // Length n of ring pair q's rings and the FFT length M (n, or the Bluestein
-// length for n not a power of two).
+// length for n not a power of two or shorter than 16, at least 16).
 void ring_lengths(const dmwf_plan* p, int q, int* n_out, int* M_out, bool* blue_out) {
     const int r = q + 1;
     const int n = r < p->nside ? 4 * r : 4 * p->nside;
-    const bool b = (n & (n - 1)) != 0;
+    const bool b = (n & (n - 1)) != 0 || n < 16;
     int M = n;
     if (b) {
-        M = 1;
+        M = 16;
         while (M < 2 * n - 1) M <<= 1;
     }
     *n_out = n;
