@@ -354,10 +354,12 @@ __device__ __forceinline__ void unfold_store(double2 zk, double2 zc, int m, doub
 
 // One workgroup per ring pair.  NT threads, E FFT elements per thread in the
 // owner layout, J of them pixels (n <= J S), MFIX the FFT length of the class
-// (0: run time).  PREF (J <= 4): the pixel data are loaded before the last
-// synthesis FFT.
+// (0: run time).  d and N^-1 of the first PJ elements are loaded before the
+// last synthesis FFT.
 template <int NT, int E, int J, int MFIX>
-__global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
+// At most 128 VGPRs (four waves per SIMD): the LDS of the classes allows
+// 16 waves per CU, and the registers must not allow fewer.
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_ring_fft(RingArgs a) {
     extern __shared__ double2 buf[];
     __shared__ double2 red[NT / 64];
     __shared__ double2 tw[128];
@@ -405,15 +407,16 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
     const bool act = tid < S;
     // modes per thread and batch in the fold
     constexpr int FB = NT >= 512 ? 4 : 6;
-    constexpr bool PREF = J <= 4;
+    constexpr bool CHR = J <= 4;
+    constexpr int PJ = J < 4 ? J : 4;
 
     double2 x[E];
     const bool syn = (a.mode == RING_SYN || a.mode == RING_ITER || a.mode == RING_SYN_WRES);
     // Chirp of a Bluestein ring at the thread's elements (k < n <= J S): with
-    // PREF held in registers for its four uses (fold input, pixel output,
+    // CHR held in registers for its four uses (fold input, pixel output,
     // pixel input, analysis output), else loaded at each use.
-    double2 chr[PREF ? J : 1];
-    if constexpr (PREF) {
+    double2 chr[CHR ? J : 1];
+    if constexpr (CHR) {
 #pragma unroll
         for (int e = 0; e < J; ++e) {
             const int k = tid + e * S;
@@ -421,7 +424,7 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
         }
     }
     auto chirp = [&](int e) -> double2 {
-        if constexpr (PREF) return chr[e < J ? e : 0];
+        if constexpr (CHR) return chr[e < J ? e : 0];
         else return ch[tid + e * S];
     };
     root_table<NT>(tw, M, tid);  // read after the barriers of the input stage
@@ -489,28 +492,25 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
         // Each DFT is one FFT, or two around the filter product for Bluestein
         // rings.  Memory that a later step needs is loaded before the FFT
         // that precedes it, so that its latency hides behind the FFT: the
-        // filter spectrum, and (PREF: few pixel elements per thread) the
-        // pixel data of the pixel step.
-        double pd[PREF ? 4 * J : 1];
+        // filter spectrum, and d and N^-1 of the pixel step's first elements.
+        double pd[4 * PJ];
         if (blue) {
             double2 bq[E];
             if (act) load_owner<E>(bq, B, tid, S);
             fft_owner<E, MFIX>(x, buf, M, logM, tid, tw);
             if (act) filter_regs<E>(x, M, bq);
         }
-        if constexpr (PREF) {
 #pragma unroll
-            for (int e = 0; e < J; ++e) {
-                const int j = tid + e * S;
-                double* v = pd + 4 * e;
-                v[0] = v[1] = v[2] = v[3] = 0.0;
-                if (act && j < n && a.mode != RING_SYN) {
-                    v[0] = dd[st0 + j];
-                    v[1] = ww[st0 + j];
-                    if (!eq) {
-                        v[2] = dd[st1 + j];
-                        v[3] = ww[st1 + j];
-                    }
+        for (int e = 0; e < PJ; ++e) {
+            const int j = tid + e * S;
+            double* v = pd + 4 * e;
+            v[0] = v[1] = v[2] = v[3] = 0.0;
+            if (act && j < n && a.mode != RING_SYN) {
+                v[0] = dd[st0 + j];
+                v[1] = ww[st0 + j];
+                if (!eq) {
+                    v[2] = dd[st1 + j];
+                    v[3] = ww[st1 + j];
                 }
             }
         }
@@ -535,8 +535,8 @@ __global__ __launch_bounds__(NT) void k_ring_fft(RingArgs a) {
                     const double2 y = blue ? cmul(chirp(e), x[e]) : conj2(x[e]);
                     yN[u] = y.x;
                     yS[u] = y.y;
-                    if constexpr (PREF) {
-                        const double* v = pd + 4 * (e < J ? e : 0);
+                    if (e < PJ) {
+                        const double* v = pd + 4 * (e < PJ ? e : 0);
                         dN[u] = v[0];
                         wN[u] = v[1];
                         dS[u] = v[2];
