@@ -17,7 +17,8 @@
  *   F    = Omega Y^H  Omega = 4 pi / Npix times the adjoint of Y
  *
  * and the harmonic step is taken in residual form (see dmwf_dm_iterate).
- * Everything is FP64 on one GPU.
+ * Everything is FP64 on one GPU, except the Legendre contractions of plans
+ * created with a reduced precision (dmwf_precision).
  *
  * Conventions shared by every entry point
  *   Maps    [nmaps][Npix] doubles, HEALPix RING order, Npix = 12 nside^2.
