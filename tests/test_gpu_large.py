@@ -2,9 +2,11 @@
 
 Full transforms up to Nside 512; at the paper-scale Nside 1024 / lmax 2048
 (the benchmark's launch configuration) the oracle evaluates sampled rings and
-sampled m one by one, and one full iteration through the C ABI is checked
-against an oracle iteration.  The batched workload's Nside 512 group is
-checked the same way in its autotuned launch configuration.
+sampled m one by one, one full iteration through the C ABI is checked
+against an oracle iteration, and solves replayed across level switches
+(Nside 1024 and 256) are checked in a, s and the FP64 residual.  The batched
+workload's Nside 512 group is checked the same way in its autotuned launch
+configuration.
 """
 import math
 
@@ -177,6 +179,8 @@ def test_batched_nside512_group_sampled():
     alm, smap, sts = plan.solve(torch.tensor(cl, device=dev), torch.tensor(d, device=dev),
                                 torch.tensor(w, device=dev), start_final=True, alm=a0,
                                 replay=[1])
+    res = plan.wf_residual(torch.tensor(cl, device=dev), torch.tensor(d, device=dev),
+                           torch.tensor(w, device=dev), alm)
     alm, smap = alm.cpu().numpy(), smap.cpu().numpy()
     for k in range(2):
         ref = dm.solve(T, d[k], w[k], cl[k], start_final=True, alm0=np.zeros_like(alm[k]),
@@ -184,6 +188,8 @@ def test_batched_nside512_group_sampled():
         assert sts[k].n_iter == 1 and ref.n_iter == 1
         assert rel(alm[k], ref.alm) < 1e-11
         assert rel(smap[k], ref.map) < 1e-11
+        # the batched residual of map k against the oracle's
+        assert res[k] == pytest.approx(dm.wf_residual(T, ref.alm, d[k], w[k], cl[k]), rel=1e-8)
 
 
 def _solve_and_replay(nside, name, mu0, replay_gpu, replay_oracle, cap, ring_list):
@@ -209,6 +215,13 @@ def _solve_and_replay(nside, name, mu0, replay_gpu, replay_oracle, cap, ring_lis
     for r in ring_list:  # every sampled ring on its own
         sl = slice(start[r - 1], start[r - 1] + nph[r - 1])
         assert rel(smap[sl], ref.map[sl]) < 1e-10, r
+    # the FP64 residual of the Wiener filter system at the solve's end point
+    # (its own ring-stage modes: synthesis with the weighted residual, then
+    # the weighted-data analysis) against the oracle's at the oracle's
+    got = plan.wf_residual(to_dev(p.cl, dev), to_dev(d, dev), to_dev(w, dev), to_dev(alm, dev))
+    want = dm.wf_residual(T, ref.alm, d, w, p.cl)
+    print(f"nside {nside}: wf_residual {got:.6e} oracle {want:.6e}")
+    assert got == pytest.approx(want, rel=1e-8)
     return st, ref, p
 
 
