@@ -20,6 +20,10 @@ constexpr int kLegWaves = DMWF_LEG_WAVES;
 // l values per block of the Legendre kernels: recurrences start only at the
 // first l of a block (counted from m), and the analysis reduces once per block.
 constexpr int kLegB = 16;
+// Launch classes of the ring stage (by FFT length; ring.hip), and the side
+// streams they run on beside the caller's
+constexpr int kRingClasses = 5;
+constexpr int kRingSide = 3;
 // Padding (entries) after the per-(l,m) tables so that look-ahead reads of
 // the recurrence coefficients stay inside the allocation.
 constexpr int kTablePad = 64;
@@ -162,13 +166,13 @@ struct dmwf_plan {
     double2* d_chirp = nullptr;        // e^{i pi t^2 / n}, t < n, per Bluestein ring
     double2* d_bspec = nullptr;        // FFT_M of the chirp filter, per Bluestein ring
     int* d_ring_class = nullptr;       // q lists of the launch classes, concatenated
-    int class_off[5] = {0, 0, 0, 0, 0};
+    int class_off[dmwf::kRingClasses + 1] = {};
     // side streams (default priority) on which the smaller launch classes run
     // concurrently with the largest, forked from and joined to the caller's
     // stream with events
-    hipStream_t ring_side[3] = {nullptr, nullptr, nullptr};
+    hipStream_t ring_side[dmwf::kRingSide] = {};
     hipEvent_t ring_fork = nullptr;
-    hipEvent_t ring_join[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ring_join[dmwf::kRingSide] = {};
     dmwf::WsLayout ws;
     // pinned host copy of the control block, read after each batch of the
     // solve loop (two batches in flight)
@@ -321,6 +325,5 @@ dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const RingMa
 // Ring transform tables and launch classes; called by dmwf_plan_create.
 dmwf_status build_ring_tables(dmwf_plan* p);
 void free_ring_tables(dmwf_plan* p);
-constexpr int kRingClasses = 4;
 
 }  // namespace dmwf

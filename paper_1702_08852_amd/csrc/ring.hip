@@ -26,8 +26,10 @@
 // c = xi w / (1 + (xi - alpha) w) (messenger step with N_bar = N - alpha)
 // and analyses r into G, overwriting F in place.
 //
-// Workgroups are launched in four classes by FFT length (LDS size) so that
-// small rings do not reserve the LDS of the largest; within a class the ring
+// Workgroups are launched in five classes by FFT length (M <= 512, 1024,
+// 2048, 4096, 8192), so that small rings neither reserve the LDS of the
+// largest nor leave threads of a larger class's workgroup idle; within a
+// class the ring
 // pairs are ordered so that consecutive pairs land on the same XCD and share
 // its L2 for the neighbouring F/G lines.
 #include <algorithm>
@@ -700,23 +702,24 @@ __global__ __launch_bounds__(NT) void k_chirp_spectrum(const int* __restrict__ q
     }
 }
 
-int ring_class(int M) { return M <= 1024 ? 0 : (M == 2048 ? 1 : (M == 4096 ? 2 : 3)); }
+int ring_class(int M) {
+    return M <= 512 ? 0 : (M == 1024 ? 1 : (M == 2048 ? 2 : (M == 4096 ? 3 : 4)));
+}
 
 // Launch shape per class: threads and FFT elements per thread (one radix-E
 // butterfly per thread and pass at the largest length of the class); the FFT
-// length is fixed at compile time except in the class of short rings.  Eight
+// length is fixed at compile time except in the class of short rings
+// (M <= 512, one wave).  Eight
 // elements per thread (four passes at M = 4096) measured faster than sixteen
 // (three passes): half the registers, so twice the waves per CU.
-constexpr int kClassE[kRingClasses] = {8, 8, 8, 8};
-constexpr int kClassMaxM[kRingClasses] = {1024, 2048, 4096, 8192};
-constexpr int kClassThreads[kRingClasses] = {kClassMaxM[0] / kClassE[0], kClassMaxM[1] / kClassE[1],
-                                             kClassMaxM[2] / kClassE[2], kClassMaxM[3] / kClassE[3]};
+constexpr int kClassE[kRingClasses] = {8, 8, 8, 8, 8};
+constexpr int kClassMaxM[kRingClasses] = {512, 1024, 2048, 4096, 8192};
 
 template <int C>
 void launch_one(dim3 grid, size_t lds, hipStream_t s, const RingArgs& a) {
-    constexpr int E = kClassE[C], NT = kClassThreads[C];
+    constexpr int E = kClassE[C], NT = kClassMaxM[C] / E;
     // the Bluestein class has n <= M / 2: half the elements are pixels
-    constexpr int J = C == 3 ? E / 2 : E;
+    constexpr int J = C == kRingClasses - 1 ? E / 2 : E;
     constexpr int MF = C == 0 ? 0 : kClassMaxM[C];
     hipLaunchKernelGGL((k_ring_fft<NT, E, J, MF>), grid, dim3(NT), lds, s, a);
 }
@@ -726,7 +729,8 @@ void launch_class(int cls, dim3 grid, size_t lds, hipStream_t s, const RingArgs&
         case 0: launch_one<0>(grid, lds, s, a); break;
         case 1: launch_one<1>(grid, lds, s, a); break;
         case 2: launch_one<2>(grid, lds, s, a); break;
-        default: launch_one<3>(grid, lds, s, a); break;
+        case 3: launch_one<3>(grid, lds, s, a); break;
+        default: launch_one<4>(grid, lds, s, a); break;
     }
 }
 
@@ -764,7 +768,7 @@ void free_ring_tables(dmwf_plan* p) {
                     p->d_bspec,  p->d_ring_class};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < kRingSide; ++i) {
         if (p->ring_side[i]) (void)hipStreamDestroy(p->ring_side[i]);
         if (p->ring_join[i]) (void)hipEventDestroy(p->ring_join[i]);
     }
@@ -815,7 +819,7 @@ dmwf_status build_ring_tables(dmwf_plan* p) {
         append_xcd_order(lists[c], all);
     }
     p->class_off[kRingClasses] = (int)all.size();
-    for (int i = 0; i < kRingClasses - 1; ++i) {
+    for (int i = 0; i < kRingSide; ++i) {
         DMWF_HIP(hipStreamCreateWithFlags(&p->ring_side[i], hipStreamNonBlocking));
         DMWF_HIP(hipEventCreateWithFlags(&p->ring_join[i], hipEventDisableTiming));
     }
@@ -889,25 +893,30 @@ dmwf_status launch_ring(dmwf_plan* p, RingMode mode, double2* spec, const RingMa
         case RING_ANA_WD: a.pix = PIX_WD; break;
         case RING_ANA_CRES: a.pix = PIX_CRES; break;
     }
-    // The largest class runs on the caller's stream, the others on side
-    // streams forked from it, so that all four share the GPU; the caller's
-    // stream then waits for every side stream.
+    // The largest non-empty class runs on the caller's stream, the next ones
+    // on side streams forked from it, and the caller's stream then waits for
+    // every side stream.  At most kRingSide side streams: further (smaller)
+    // classes follow the last one on its stream, so that the classes of a
+    // launch never need more than four queues.
     ProfScope ps(p, s, cls);
     DMWF_HIP(hipEventRecord(p->ring_fork, s));
+    int rank = 0;
     for (int c = kRingClasses - 1; c >= 0; --c) {
         const int nb = off[c + 1] - off[c];
         if (nb == 0) continue;
+        const int side = rank == 0 ? -1 : std::min(rank - 1, kRingSide - 1);
+        ++rank;
         hipStream_t sc = s;
-        if (c < kRingClasses - 1) {
-            sc = p->ring_side[c];
+        if (side >= 0) {
+            sc = p->ring_side[side];
             DMWF_HIP(hipStreamWaitEvent(sc, p->ring_fork, 0));
         }
         a.qlist = qlists + off[c];
         launch_class(c, dim3(nb, rm.nm), class_lds(c), sc, a);
         DMWF_HIP(hipGetLastError());
-        if (c < kRingClasses - 1) {
-            DMWF_HIP(hipEventRecord(p->ring_join[c], sc));
-            DMWF_HIP(hipStreamWaitEvent(s, p->ring_join[c], 0));
+        if (side >= 0) {
+            DMWF_HIP(hipEventRecord(p->ring_join[side], sc));
+            DMWF_HIP(hipStreamWaitEvent(s, p->ring_join[side], 0));
         }
     }
     return DMWF_OK;
