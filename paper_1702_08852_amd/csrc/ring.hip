@@ -84,7 +84,6 @@ __device__ __forceinline__ void lds_barrier() {
 __device__ __forceinline__ int pad(int e) { return e + (e >> 4); }
 
 constexpr int ilog2(int r) { return r <= 1 ? 0 : 1 + ilog2(r >> 1); }
-__device__ __forceinline__ int ilog2_rt(int v) { return 31 - __clz(v); }
 constexpr int bitrev(int i, int bits) { return bits == 0 ? 0 : ((i & 1) << (bits - 1)) | bitrev(i >> 1, bits - 1); }
 
 // cos and sin of k pi / 8, k = 0..7
@@ -357,10 +356,9 @@ __device__ __forceinline__ void unfold_store(double2 zk, double2 zc, int m, doub
 // One workgroup per ring pair.  NT threads, E FFT elements per thread in the
 // owner layout, J of them pixels (n <= J S), MFIX the FFT length of the class
 // (0: run time).  d and N^-1 of the first PJ elements are loaded before the
-// last synthesis FFT.
+// last synthesis FFT.  At most 128 VGPRs (four waves per SIMD): the LDS of
+// the classes allows 16 waves per CU, and the registers must not allow fewer.
 template <int NT, int E, int J, int MFIX>
-// At most 128 VGPRs (four waves per SIMD): the LDS of the classes allows
-// 16 waves per CU, and the registers must not allow fewer.
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_ring_fft(RingArgs a) {
     extern __shared__ double2 buf[];
     __shared__ double2 red[NT / 64];
