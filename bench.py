@@ -281,6 +281,29 @@ def bench_configs(dev, with_cpu):
                "gate": "Cauchy ratio < eps_final at xi = alpha (Algorithm 2's stopping rule)",
                "residual_target": p.eps_final}
         rec["residual_target_met"] = bool(rec["wf_residual"] <= p.eps_final)
+        if not rec["residual_target_met"]:
+            # Continue the last level (xi = alpha) from the solution with a
+            # tenfold tighter Cauchy tolerance until the FP64 residual meets
+            # the figure the configuration names (at most four rounds).
+            a_c, eps_c, iters, t_c = alm, p.eps_final, 0, 0.0
+            resid = rec["wf_residual"]
+            rounds = 0
+            while resid > p.eps_final and rounds < 4:
+                eps_c /= 10.0
+                rounds += 1
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                a_c, _, st_c = plan.solve(cl, d, w, eps_final=eps_c, start_final=True,
+                                          alm=a_c.clone())
+                torch.cuda.synchronize()
+                t_c += time.perf_counter() - t0
+                iters += st_c.n_iter
+                resid = plan.wf_residual(cl, d, w, a_c)
+            rec["residual_continuation"] = {
+                "how": "last level continued from the solution, Cauchy tolerance / 10 per round",
+                "rounds": rounds, "final_eps": eps_c, "extra_iterations": iters,
+                "extra_seconds": t_c, "wf_residual": resid,
+                "residual_target_met": bool(resid <= p.eps_final)}
         if with_cpu:
             T = oracle.SphereTransforms(nside, lmax)
             dh, wh = d.cpu().numpy(), w.cpu().numpy()

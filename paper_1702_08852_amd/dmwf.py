@@ -264,8 +264,9 @@ class Plan:
                "dmwf_set_tiles")
 
     def set_pipeline(self, groups: int) -> None:
-        """Split the iteration's synthesis and ring stage into this many
-        ring-pair groups that overlap (0 or 1: off)."""
+        """dmwf_set_pipeline, kept for ABI stability: the pipelined iteration
+        is not built, so only 0 and 1 (off) are accepted; 2..8 raise with
+        DMWF_ERR_UNSUPPORTED."""
         _check(load().dmwf_set_pipeline(self._h, int(groups)), "dmwf_set_pipeline")
 
     @property
