@@ -15,7 +15,10 @@ pytestmark = pytest.mark.gpu
 # The pipelined path is switched off and its internals are removed from the
 # library: its first solve (nside 128, one map, two groups) ended the test
 # process with a host segmentation fault inside dmwf_solve, and no cause was
-# found in the host code.  The tests that ran it stay here, skipped.
+# found in the host code.  Its ring stage forked side streams from a stream
+# that had joined the graph capture through an event; a later variant of the
+# multi-plan solve with that same shape faulted the same way.  The tests that
+# ran it stay here, skipped.
 OFF = ("pipelined iteration switched off (removed): host segmentation fault in its first solve, "
        "cause not found")
 
