@@ -2,7 +2,7 @@
  * dmwf.h -- C ABI of the MI355X dual messenger Wiener filter library.
  *
  * The library solves the Wiener filter equation of Kodi Ramanah, Lavaux &
- * Wandelt (2017), eq. (wf_equation),
+ * Wandelt (2017), Section 1,
  *
  *        (S^-1 + N^-1) s_WF = N^-1 d,
  *
@@ -75,7 +75,7 @@ typedef enum { DMWF_FP64 = 0, DMWF_FP32_GEMM = 1, DMWF_BF16X3_GEMM = 2 } dmwf_pr
 typedef struct dmwf_plan dmwf_plan;
 
 typedef struct {
-    int nside;     /* power of two, 1 .. 8192                                  */
+    int nside;     /* power of two, 1 .. 8192 (above 1024: DMWF_ERR_UNSUPPORTED) */
     int lmax;      /* 0 .. 3 nside - 1                                         */
     int nmaps;     /* 1 .. 65535; the maps of a plan are transformed and solved together */
     int precision; /* dmwf_precision                                           */

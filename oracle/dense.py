@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Paper eq. (wf_equation): (S^-1 + N^-1) s_WF = N^-1 d for the data model
-d = s + n.  On the sphere the signal is s = Y a with S = diag(C_l) in the a_lm
+The Wiener filter equation of the paper's Section 1, (S^-1 + N^-1) s_WF = N^-1 d,
+for the data model d = s + n.  On the sphere the signal is s = Y a with S = diag(C_l) in the a_lm
 basis, so with W = N^-1 (zero on masked pixels) the same equation reads, in
 harmonic space,
 
