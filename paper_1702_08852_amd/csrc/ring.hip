@@ -29,9 +29,8 @@
 // Workgroups are launched in five classes by FFT length (M <= 512, 1024,
 // 2048, 4096, 8192), so that small rings neither reserve the LDS of the
 // largest nor leave threads of a larger class's workgroup idle; within a
-// class the ring
-// pairs are ordered so that consecutive pairs land on the same XCD and share
-// its L2 for the neighbouring F/G lines.
+// class the ring pairs are ordered so that consecutive pairs land on the same
+// XCD and share its L2 for the neighbouring F/G lines.
 #include <algorithm>
 #include <cmath>
 #include <vector>
