@@ -311,14 +311,16 @@ __device__ __forceinline__ double xsum32(double a, double b) {
     return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
 }
 
-// Sum of v over the four lanes i, i ^ 16, i ^ 32, i ^ 48, returned in all four.
-__device__ __forceinline__ double xsum_rows(double v) {
-    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false,
+// Sums of a over the four lanes i, i ^ 16, i ^ 32, i ^ 48 (lanes 0..15 and
+// 32..47) and of b likewise (lanes 16..31 and 48..63), one value per lane: the
+// row swap pairs a's rows with b's, so both sums share every instruction.
+__device__ __forceinline__ double xsum_rows2(double a, double b) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false,
                                                      false);
-    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false,
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false,
                                                      false);
-    v = __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
-    return xsum32(v, v);
+    const double c = __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+    return xsum32(c, c);
 }
 
 // Row of the analysis reduction buffer: 64 lanes' values with one pad slot
@@ -503,19 +505,24 @@ __global__ __launch_bounds__(64 * kLegWaves) void k_leg_ana(AnaArgs a) {
             double sr[MB], si[MB];
 #pragma unroll
             for (int i = 0; i < MB; ++i) {
-                sr[i] = si[i] = 0.0;
+                double2 v = red[rb >> 1][i][rcol];
+                sr[i] = v.x;
+                si[i] = v.y;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const double2 v = red[rb >> 1][i][rcol + u];
+                for (int u = 1; u < 8; ++u) {
+                    v = red[rb >> 1][i][rcol + u];
                     sr[i] += v.x;
                     si[i] += v.y;
                 }
             }
             wave_lds_sync();
+            // lanes 0..15 end with the real part of row rb, lanes 16..31 with
+            // the imaginary part, each stored as one double
 #pragma unroll
             for (int i = 0; i < MB; ++i) {
-                const double vr = xsum_rows(sr[i]), vi = xsum_rows(si[i]);
-                if (rp == 0 && l0 + rb <= ell && ellm[i] >= 0) out[i][l0 + rb] = make_double2(vr, vi);
+                const double v = xsum_rows2(sr[i], si[i]);
+                if (rp < 2 && l0 + rb <= ell && ellm[i] >= 0)
+                    reinterpret_cast<double*>(out[i] + l0 + rb)[rp] = v;
             }
         }
         cf[cur ^ 1][lane] = na;
